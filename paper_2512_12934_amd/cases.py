@@ -1,0 +1,311 @@
+"""Seeded synthetic cases (geometry, parameters, initial fields).
+
+This module describes inputs only: box sizes, solid masks, initial component
+densities, inlet/outlet patches and the physical parameters of each workload.
+It holds none of the method's arithmetic, so the FP64 oracle and the HIP
+library can both be fed from it.
+
+Node order is x fastest: ``n = x + nx*(y + ny*z)``.  Densities are
+``rho0[k, n]`` for component k in {0, 1} (the paper's components 1 and 2).
+"""
+from __future__ import annotations
+
+import copy
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    dim: int
+    n: tuple
+    periodic: tuple
+    nu: tuple
+    G12: float
+    solid: np.ndarray
+    rho0: np.ndarray
+    u0: Optional[np.ndarray] = None
+    s_q: float = 1.2
+    s_eps_policy: int = 0          # 0: most-viscous phase (paper), 1: fixed = s_nu,k
+    Gw: tuple = (0.0, 0.0)
+    Fb: tuple = (0.0, 0.0, 0.0)
+    inlets: list = dataclasses.field(default_factory=list)
+    outlet: Optional[dict] = None
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def fluid_nodes(self) -> int:
+        return int((self.solid == 0).sum())
+
+    def grid(self):
+        """Return coordinate arrays (x, y, z), each of length N."""
+        nx, ny, nz = self.n
+        z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        return x.reshape(-1), y.reshape(-1), z.reshape(-1)
+
+    def copy(self, **changes) -> "Case":
+        c = copy.deepcopy(self)
+        for k, v in changes.items():
+            setattr(c, k, v)
+        return c
+
+
+def _rho_from_mask(inside: np.ndarray, major: float, minor: float) -> np.ndarray:
+    """Component 1 is ``major`` where ``inside``; component 2 is mirrored."""
+    rho = np.empty((2, inside.size))
+    rho[0] = np.where(inside, major, minor)
+    rho[1] = np.where(inside, minor, major)
+    return rho
+
+
+def _plug(case: Case, regions) -> np.ndarray:
+    """Initial velocity: uniform plug flow ``value`` along ``axis`` on each
+    (mask, axis, value) region, zero on solids.  Starting open-boundary runs
+    from the plug flow their inlets feed keeps the inlet and outlet mass flows
+    comparable from the first step."""
+    u0 = np.zeros((3, case.N))
+    for mask, axis, value in regions:
+        u0[axis][mask] = value
+    u0[:, case.solid == 1] = 0.0
+    return u0
+
+
+def inlet(axis, side, lo, hi, rho, u_n, alpha_on=True):
+    return {"axis": axis, "side": side, "lo": tuple(lo), "hi": tuple(hi),
+            "rho": tuple(rho), "u_n": float(u_n), "alpha_on": int(bool(alpha_on))}
+
+
+def outlet(axis, side, lo, hi, chi_on=True):
+    return {"axis": axis, "side": side, "lo": tuple(lo), "hi": tuple(hi),
+            "chi_on": int(bool(chi_on))}
+
+
+# ---------------------------------------------------------------------------
+# Laplace test: static droplet, fully periodic
+# ---------------------------------------------------------------------------
+
+def laplace(n: int = 64, R: float = 16.0, G12: float = 0.9, nu=(1.0 / 6.0, 1.0 / 6.0),
+            major: float = 1.0, minor: float = 0.03, s_eps_policy: int = 0,
+            dim: int = 2, center=None) -> Case:
+    """Static droplet of radius R centred in an n^dim periodic box.
+
+    Defaults: 64x64, R = 16, G12 = 0.9, relaxation time 1 for both components
+    (nu = 1/6), droplet component density 1.0 inside / 0.03 outside and the
+    other component mirrored, u = 0.  A node is inside when its distance to
+    the centre is below R (sharp initial step)."""
+    shape = (n, n, n if dim == 3 else 1)
+    c = Case("laplace", dim, shape, (True, True, True), tuple(nu), G12,
+             solid=np.zeros(int(np.prod(shape)), np.uint8), rho0=None,
+             s_eps_policy=s_eps_policy)
+    x, y, z = c.grid()
+    cx = cy = cz = n / 2.0
+    if center is not None:
+        cx, cy = center[0], center[1]
+        if dim == 3:
+            cz = center[2]
+    r2 = (x - cx) ** 2 + (y - cy) ** 2 + ((z - cz) ** 2 if dim == 3 else 0)
+    c.rho0 = _rho_from_mask(r2 < R * R, major, minor)
+    c.meta.update(R=R, major=major, minor=minor)
+    return c
+
+
+# ---------------------------------------------------------------------------
+# Random periodic / closed boxes (for invariants and parity at several tiles)
+# ---------------------------------------------------------------------------
+
+def random_box(shape, seed: int, dim: int = 2, periodic=(True, True, True),
+               walls: bool = False, G12: float = 0.9, nu=(0.1, 0.3),
+               amp: float = 0.02, Gw=(0.0, 0.0), Fb=(0.0, 0.0, 0.0),
+               u_amp: float = 0.0) -> Case:
+    """Smooth random two-component field in a box of the given shape.
+
+    With ``walls`` every non-periodic axis gets a one-node solid shell and a
+    few solid blocks are scattered inside."""
+    rng = np.random.default_rng(seed)
+    nx, ny = shape[0], shape[1]
+    nz = shape[2] if dim == 3 else 1
+    c = Case(f"random{dim}d", dim, (nx, ny, nz), tuple(periodic), tuple(nu), G12,
+             solid=np.zeros(nx * ny * nz, np.uint8), rho0=None, Gw=tuple(Gw), Fb=tuple(Fb))
+    x, y, z = c.grid()
+    solid = np.zeros(c.N, bool)
+    if walls:
+        for a, (coord, size) in enumerate(((x, nx), (y, ny), (z, nz))):
+            if a >= dim or periodic[a]:
+                continue
+            solid |= (coord == 0) | (coord == size - 1)
+        for _ in range(3):
+            bx, by = rng.integers(2, max(3, nx - 4)), rng.integers(2, max(3, ny - 4))
+            blk = (x >= bx) & (x < bx + 2) & (y >= by) & (y < by + 2)
+            if dim == 3:
+                bz = rng.integers(2, max(3, nz - 4))
+                blk &= (z >= bz) & (z < bz + 2)
+            solid |= blk
+    c.solid = solid.astype(np.uint8)
+    # a smooth phase field: a few random Fourier modes
+    phase = np.zeros(c.N)
+    for _ in range(4):
+        kx, ky, kz = rng.integers(1, 3, size=3)
+        ph = rng.uniform(0, 2 * math.pi, size=3)
+        phase += np.sin(2 * math.pi * kx * x / nx + ph[0]) * np.cos(2 * math.pi * ky * y / ny + ph[1]) \
+            * (np.cos(2 * math.pi * kz * z / nz + ph[2]) if dim == 3 else 1.0)
+    inside = phase > 0
+    rho = _rho_from_mask(inside, 1.0, 0.05)
+    rho *= 1.0 + amp * rng.standard_normal(rho.shape)
+    c.rho0 = rho
+    if u_amp > 0:
+        u0 = np.zeros((3, c.N))
+        u0[:dim] = u_amp * rng.standard_normal((dim, c.N))
+        c.u0 = u0
+    return c
+
+
+# ---------------------------------------------------------------------------
+# Two-phase Poiseuille flow between plates (periodic along x)
+# ---------------------------------------------------------------------------
+
+def poiseuille(M: float, Fb: float, width: int = 100, a: float = 25.0, nx: int = 4,
+               nu2: float = 0.067, major: float = 1.02, minor: float = 0.03,
+               G12: float = 0.9, u_init=None, dim: int = 2) -> Case:
+    """Fluid 1 (viscosity M*nu2) in the core |y - yc| < a, fluid 2 outside, up
+    to the walls; ``width`` fluid rows between two solid rows; body force Fb
+    along x.  ``u_init`` optionally gives an initial u_x(y) profile (length
+    width) applied to every column."""
+    ny = width + 2
+    nz = 1 if dim == 2 else 4
+    c = Case("poiseuille", dim, (nx, ny, nz), (True, False, True), (M * nu2, nu2), G12,
+             solid=None, rho0=None, Fb=(Fb, 0.0, 0.0))
+    x, y, z = c.grid()
+    c.solid = ((y == 0) | (y == ny - 1)).astype(np.uint8)
+    yc = (ny - 1) / 2.0
+    inside = np.abs(y - yc) < a
+    c.rho0 = _rho_from_mask(inside, major, minor)
+    if u_init is not None:
+        u0 = np.zeros((3, c.N))
+        prof = np.zeros(ny)
+        prof[1:ny - 1] = u_init
+        u0[0] = prof[y]
+        u0[0][c.solid == 1] = 0.0
+        c.u0 = u0
+    c.meta.update(M=M, a=a, L=width / 2.0, yc=yc, major=major, minor=minor)
+    return c
+
+
+# ---------------------------------------------------------------------------
+# Straight channel with inlet and outlet (2-D or 3-D)
+# ---------------------------------------------------------------------------
+
+def channel(length: int, width: int, u_in: float, nu=(0.067, 0.067), G12: float = 0.9,
+            alpha_on=True, chi_on=True, droplet=None, major: float = 1.0,
+            minor: float = 0.03, dim: int = 2, Gw=(0.0, 0.0)) -> Case:
+    """Channel along x with walls on the other axes, inlet at x = 0 carrying
+    the continuous phase (component 2), convective outlet at x = length-1.
+    ``droplet=(cx, cy[, cz], R)`` places a component-1 droplet."""
+    ny = width + 2
+    nz = 1 if dim == 2 else width + 2
+    c = Case("channel", dim, (length, ny, nz), (False, False, False), tuple(nu), G12,
+             solid=None, rho0=None, Gw=tuple(Gw))
+    x, y, z = c.grid()
+    solid = (y == 0) | (y == ny - 1)
+    if dim == 3:
+        solid |= (z == 0) | (z == nz - 1)
+    c.solid = solid.astype(np.uint8)
+    inside = np.zeros(c.N, bool)
+    if droplet is not None:
+        if dim == 2:
+            cx, cy, R = droplet
+            inside = (x - cx) ** 2 + (y - cy) ** 2 < R * R
+        else:
+            cx, cy, cz, R = droplet
+            inside = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 < R * R
+    c.rho0 = _rho_from_mask(inside, major, minor)
+    c.u0 = _plug(c, [(np.ones(c.N, bool), 0, u_in)])
+    c.inlets = [inlet(0, 0, (0, 1, 1 if dim == 3 else 0), (1, ny - 1, nz - 1 if dim == 3 else 1),
+                      (minor, major), u_in, alpha_on)]
+    c.outlet = outlet(0, 1, (0, 1, 1 if dim == 3 else 0), (1, ny - 1, nz - 1 if dim == 3 else 1),
+                      chi_on)
+    c.meta.update(u_in=u_in, width=width)
+    return c
+
+
+# ---------------------------------------------------------------------------
+# T-junction droplet generator (2-D)
+# ---------------------------------------------------------------------------
+
+def tjunction(W: int = 100, length: int = 800, x_side: int = 150, side_width: int = 100,
+              side_len: int = 100, u_c: float = 0.01, u_d: float = 0.005,
+              nu=(0.067, 0.067), G12: float = 0.9, Gw_mag: float = 0.0,
+              major: float = 1.0, minor: float = 0.03, alpha_on=True, chi_on=True) -> Case:
+    """Main channel ``length`` x ``W`` fluid nodes between solid rows y = 0 and
+    y = W+1, side channel of width ``side_width`` over x in
+    [x_side, x_side+side_width) rising ``side_len`` rows above the main
+    channel.  Continuous phase (component 2) enters at x = 0 with u_c;
+    dispersed phase (component 1) enters through the top of the side channel
+    with u_d (downwards); convective outlet at x = length-1.  Walls repel the
+    dispersed phase with adhesion +Gw_mag and attract the continuous phase
+    with -Gw_mag."""
+    nx = length
+    ny = W + 2 + side_len
+    c = Case("tjunction", 2, (nx, ny, 1), (False, False, False), tuple(nu), G12,
+             solid=None, rho0=None, Gw=(Gw_mag, -Gw_mag))
+    x, y, _ = c.grid()
+    main = (y >= 1) & (y <= W)
+    side = (x >= x_side) & (x < x_side + side_width) & (y > W)
+    fluid = main | side
+    c.solid = (~fluid).astype(np.uint8)
+    c.rho0 = _rho_from_mask(side, major, minor)
+    down = (x >= x_side) & main
+    c.u0 = _plug(c, [(main & ~down, 0, u_c),
+                     (down, 0, u_c + u_d * side_width / W),
+                     (side, 1, -u_d)])
+    c.inlets = [
+        inlet(0, 0, (0, 1, 0), (1, W + 1, 1), (minor, major), u_c, alpha_on),
+        inlet(1, 1, (x_side, 0, 0), (x_side + side_width, 1, 1), (major, minor), u_d, alpha_on),
+    ]
+    c.outlet = outlet(0, 1, (0, 1, 0), (1, W + 1, 1), chi_on)
+    c.meta.update(W=W, u_c=u_c, u_d=u_d, x_side=x_side, side_width=side_width)
+    return c
+
+
+# ---------------------------------------------------------------------------
+# 3-D co-flow device (square channel, coaxial dispersed-phase inlet)
+# ---------------------------------------------------------------------------
+
+def coflow3d(length: int = 600, width: int = 120, inner: int = 30, u_c: float = 0.02,
+             u_d: float = 0.005, nu_c: float = 0.067, M: float = 5.0, G12: float = 0.9,
+             Gw_mag: float = 0.0, major: float = 1.0, minor: float = 0.03,
+             alpha_on=True, chi_on=True) -> Case:
+    """Square channel of ``width`` x ``width`` fluid nodes (one-node solid
+    shell, so the box is length x (width+2) x (width+2)).  The x = 0 face is
+    the continuous-phase inlet (u_c); an ``inner`` x ``inner`` patch centred on
+    it carries the dispersed phase (u_d).  Dispersed viscosity M * nu_c."""
+    n1 = width + 2
+    c = Case("coflow3d", 3, (length, n1, n1), (False, False, False), (M * nu_c, nu_c), G12,
+             solid=None, rho0=None, Gw=(Gw_mag, -Gw_mag))
+    x, y, z = c.grid()
+    solid = (y == 0) | (y == n1 - 1) | (z == 0) | (z == n1 - 1)
+    c.solid = solid.astype(np.uint8)
+    c.rho0 = _rho_from_mask(np.zeros(c.N, bool), major, minor)
+    lo = 1 + (width - inner) // 2
+    hi = lo + inner
+    u_mean = (u_c * (width * width - inner * inner) + u_d * inner * inner) / (width * width)
+    c.u0 = _plug(c, [(np.ones(c.N, bool), 0, u_mean)])
+    c.inlets = [
+        inlet(0, 0, (0, 1, 1), (1, n1 - 1, n1 - 1), (minor, major), u_c, alpha_on),
+        inlet(0, 0, (0, lo, lo), (1, hi, hi), (major, minor), u_d, alpha_on),
+    ]
+    c.outlet = outlet(0, 1, (0, 1, 1), (1, n1 - 1, n1 - 1), chi_on)
+    c.meta.update(width=width, inner=inner, u_c=u_c, u_d=u_d, M=M)
+    return c
+
+
+def coflow3d_quarter(**kw) -> Case:
+    """The 1/4-scale copy of the co-flow device: 150 x 30 x 30 fluid, 8 x 8 inner patch."""
+    return coflow3d(length=150, width=30, inner=8, **kw)
