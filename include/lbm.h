@@ -1,0 +1,164 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) two-component immiscible
+ * pseudopotential MRT lattice Boltzmann solver with corrected open boundaries
+ * (Chen, Pan, Wang, Li & Chen, arXiv:2512.12934).
+ *
+ * One call of lbm_step advances the lattice by whole time steps of the method
+ * of Sec. II: densities and pseudopotentials (eq. 8; psi_k = rho_k) with
+ * mirror ghost layers at open faces (eqs. 24-25), the fluid-fluid force of
+ * eq. (10) with the 8th-order weights of Sec. II A and the wall adhesion of
+ * eq. (11), the common velocity (eqs. 7-8), the outlet velocity correction
+ * from the inlet/outlet mass-flow ratio (eqs. 22-23, App. A), the MRT
+ * collision with forcing (eqs. 1, 3-6, 9) with s_e and s_eps taken from the
+ * most viscous phase (Sec. III A), streaming with halfway bounce-back and
+ * periodic wrap (eq. 2, App. B), the alpha-corrected non-equilibrium
+ * extrapolation inlet (eqs. 13-19) and the convective outflow (eqs. 20-21).
+ *
+ * Conventions shared by every entry point
+ *   - All calls return lbm_status; nothing throws across the ABI.
+ *   - Node index n = x + n[0]*(y + n[1]*z) over the box; 2-D uses n[2] = 1.
+ *   - Component k in {0, 1} is the paper's component k+1.
+ *   - Populations: D2Q9 order 0 (0,0); 1 (1,0); 2 (0,1); 3 (-1,0); 4 (0,-1);
+ *     5 (1,1); 6 (-1,1); 7 (-1,-1); 8 (1,-1)  (the unknown sets of Sec. II B).
+ *     D3Q19 order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (1,1,0),
+ *     (-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),
+ *     (0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1).
+ *   - The state of a context is the post-streaming, post-boundary
+ *     distribution f(t); lbm_get_state/lbm_set_state exchange it as
+ *     double f[2][Q][N] (solid nodes ignored on input, zero on output).
+ *   - Lattice units throughout.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,     /* invalid argument or configuration; nothing changed   */
+    LBM_ENOMEM = 2,     /* workspace too small or device allocation failed      */
+    LBM_EDEVICE = 3,    /* a HIP runtime call failed (message in lbm_last_error) */
+    LBM_EUNSTABLE = 4,  /* a non-finite or non-positive density was produced    */
+    LBM_ESTATE = 5      /* the context was already flagged unstable             */
+} lbm_status;
+
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16_OFFSET = 1 };
+enum { LBM_SEPS_MAXVISC = 0, LBM_SEPS_FIXED = 1 };
+#define LBM_MAX_INLETS 8
+
+/* Inlet patch (eqs. 13-19): the fluid nodes of the face layer (axis, side)
+ * whose two tangential coordinates lie in [lo, hi) (the normal coordinate of
+ * lo/hi is ignored).  side 0 is coordinate 0, side 1 is n[axis]-1.  Later
+ * patches take precedence where rectangles overlap.  rho[k] and the speed
+ * u_n along the inward normal are the prescribed inlet quantities. */
+typedef struct {
+    int axis, side;
+    int lo[3], hi[3];
+    double rho[2];
+    double u_n;
+    int alpha_on;       /* 1: eqs. (15)-(19) correction; 0: eq. (13)/(14) only */
+} lbm_inlet;
+
+/* Outlet (eqs. 20-23): fluid nodes of the face layer (axis, side) in [lo, hi). */
+typedef struct {
+    int axis, side;
+    int lo[3], hi[3];
+    int chi_on;         /* 1: mass-flow velocity correction of eqs. (22)-(23) */
+} lbm_outlet;
+
+/* Problem description.  Every array is host memory owned by the caller and
+ * copied by lbm_create. */
+typedef struct {
+    int dim;                 /* 2: D2Q9, 3: D3Q19 */
+    int storage;             /* LBM_STORE_F32 or LBM_STORE_F16_OFFSET (f - w_i in binary16) */
+    int n[3];                /* box size; n[2] = 1 in 2-D; non-periodic axes need n >= 3 */
+    int periodic[3];
+    double nu[2];            /* kinematic viscosities, eq. (5); > 0 */
+    double s_q;              /* energy-flux relaxation rate, in (0, 2) */
+    int s_eps_policy;        /* LBM_SEPS_MAXVISC (paper) or LBM_SEPS_FIXED */
+    double G12;              /* eq. (10) */
+    double Gw[2];            /* eq. (11), constant per component */
+    double Fb[3];            /* body-force density, shared as (rho_k/rho) Fb */
+    int n_inlets;
+    lbm_inlet inlets[LBM_MAX_INLETS];
+    int has_outlet;
+    lbm_outlet outlet;
+    const uint8_t *solid;    /* [N], 1 = solid; every fluid node on a
+                                non-periodic face must belong to a patch */
+    const double *rho0;      /* [2][N] initial component densities (> 0 on fluid) */
+    const double *u0;        /* [3][N] initial velocity, or NULL for rest */
+} lbm_config;
+
+/* FP64 diagnostics of the most recent step (device-side reductions). */
+typedef struct {
+    int64_t step;
+    double q_in;     /* sum over inlet nodes of rho u . n_inward      (eq. 23 numerator)   */
+    double q_out;    /* sum over the x_{N-1} column of rho u . n_out  (eq. 23 denominator) */
+    double chi;      /* eq. (23) coefficient applied (1 if uncorrected or undefined) */
+    double u_conv;   /* eq. (21) convective velocity after the clamp at 0 */
+    double mass[2];  /* current total mass of each component over fluid nodes */
+    double mass0[2]; /* total mass at creation */
+    int64_t uc_clamps;
+} lbm_flux;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of device workspace lbm_create needs for cfg; 0 if cfg is invalid. */
+size_t lbm_workspace_bytes(const lbm_config *cfg);
+
+/* Validates cfg, carves the caller-owned device buffer dev_ws (ws_bytes long,
+ * 256-byte aligned, it must outlive the context), uploads the static node
+ * maps and initialises f = feq(rho0, u0) on hip_stream (a hipStream_t owned
+ * by the caller; NULL = default stream).  Returns LBM_EINVAL for an invalid
+ * configuration, LBM_ENOMEM when ws_bytes is too small, LBM_EDEVICE on a HIP
+ * error.  On success *out receives the context. */
+lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes,
+                      void *hip_stream, lbm_ctx **out);
+
+/* Enqueues n >= 0 time steps on the context stream and returns without
+ * waiting.  Errors raised on the device surface at the next synchronising
+ * call.  LBM_ESTATE if the context was already flagged unstable. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Synchronises the stream and writes rho [2][N] and the common velocity
+ * u [3][N] of eqs. (7)-(8) (half-force included, before any outlet
+ * override) of the current state; solid nodes get 0.  Buffers are caller
+ * owned, device memory if dst_on_device != 0, else host memory.  Returns
+ * LBM_EUNSTABLE if the instability flag is set (the fields are still
+ * written). */
+lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *u, int dst_on_device);
+
+/* Synchronises and fills *out (host) with the FP64 diagnostics. */
+lbm_status lbm_mass_flux(lbm_ctx *ctx, lbm_flux *out);
+
+/* Checkpoint of the current state as host double f[2][Q][N] (bytes must be
+ * 16*Q*N).  lbm_set_state replaces the state (used for restarts and to plant
+ * values from the host); it also clears the instability flag. */
+lbm_status lbm_get_state(lbm_ctx *ctx, double *f_host, size_t bytes);
+lbm_status lbm_set_state(lbm_ctx *ctx, const double *f_host, size_t bytes);
+
+/* Measurement hook: enqueues n steps like lbm_step, bracketing every kernel
+ * launch with HIP events on the context stream, then synchronises and writes
+ * the mean duration in milliseconds of each launch kind into ms[4]:
+ * [0] the fused node update, [1] the outlet collision, [2] the inlet
+ * reconstruction, [3] the outlet fill (0 where a kind is not launched). */
+lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *ms);
+
+/* Number of steps taken; the stream is not synchronised. */
+int64_t lbm_steps_done(const lbm_ctx *ctx);
+
+/* Releases the context (not the caller's workspace).  NULL is ignored. */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Last error message of ctx (or of the last failed lbm_create if ctx is NULL). */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

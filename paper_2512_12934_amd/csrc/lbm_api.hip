@@ -1,0 +1,671 @@
+// lbm_api.hip -- host runtime and C ABI of the HIP lattice Boltzmann solver.
+//
+// The context owns nothing but a carve-up of the caller's device workspace:
+// two population arrays (source / destination of the pull-scheme step), the
+// static node map, the face buffers of the open boundaries and the FP64
+// reduction scratch.  lbm_step only enqueues kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int TX2 = 64, TY2 = 8;            // D2Q9 tile
+constexpr int TX3 = 32, TY3 = 8, TZ3 = 4;   // D3Q19 tile
+constexpr size_t ALIGN = 256;
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    int dim = 0, Q = 0, storage = 0;
+    Geometry g{};
+    int tiles[3] = {1, 1, 1};
+    int64_t nblocks_main = 0;
+    int64_t n_slots = 0, n_in = 0, n_out = 0;
+    int nb_in = 0, nb_out = 0;
+    int nb_mass = 0;
+    bool boundary = false;
+    // byte offsets into the workspace
+    size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
+        o_flag, o_mpart, o_mout, total;
+};
+
+// Host-side static maps built from the configuration.
+struct Maps {
+    std::vector<uint32_t> type;
+    std::vector<int32_t> bslot;
+    std::vector<InletRec> in;
+    std::vector<OutletRec> out;
+};
+
+int lat_Q(int dim) { return dim == 2 ? 9 : 19; }
+
+template <int DIM> void lat_e(int i, int *e)
+{
+    for (int d = 0; d < 3; d++) e[d] = Lat<DIM>::E[i][d];
+}
+
+void dir(int dim, int i, int *e)
+{
+    if (dim == 2) lat_e<2>(i, e);
+    else lat_e<3>(i, e);
+}
+
+bool on_face(const lbm_config *c, const int *xc, int axis, int side, const int *lo, const int *hi)
+{
+    const int layer = side == 0 ? 0 : c->n[axis] - 1;
+    if (xc[axis] != layer) return false;
+    for (int a = 0; a < c->dim; a++) {
+        if (a == axis) continue;
+        if (xc[a] < lo[a] || xc[a] >= hi[a]) return false;
+    }
+    return true;
+}
+
+// Validates the configuration and builds the node maps.  Returns an empty
+// string on success, else the reason.
+std::string build_maps(const lbm_config *c, Maps &m)
+{
+    if (!c) return "null configuration";
+    if (c->dim != 2 && c->dim != 3) return "dim must be 2 or 3";
+    if (c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F16_OFFSET) return "unknown storage";
+    const int nz = c->dim == 2 ? 1 : c->n[2];
+    if (c->dim == 2 && c->n[2] != 1) return "2-D boxes need n[2] == 1";
+    for (int a = 0; a < c->dim; a++) {
+        if (c->n[a] < 3) return "every lattice axis needs at least 3 nodes";
+        if (c->n[a] > (1 << 24)) return "axis too long";
+    }
+    if (!(c->nu[0] > 0.0) || !(c->nu[1] > 0.0)) return "viscosities must be positive";
+    if (!(c->s_q > 0.0 && c->s_q < 2.0)) return "s_q must lie in (0, 2)";
+    if (c->s_eps_policy != LBM_SEPS_MAXVISC && c->s_eps_policy != LBM_SEPS_FIXED) return "unknown s_eps policy";
+    if (c->n_inlets < 0 || c->n_inlets > LBM_MAX_INLETS) return "bad inlet count";
+    if (!c->solid || !c->rho0) return "solid and rho0 arrays are required";
+    for (int q = 0; q < c->n_inlets; q++) {
+        const lbm_inlet &p = c->inlets[q];
+        if (p.axis < 0 || p.axis >= c->dim || (p.side != 0 && p.side != 1)) return "bad inlet face";
+        if (c->periodic[p.axis]) return "inlet on a periodic axis";
+        if (!(p.rho[0] >= 0.0) || !(p.rho[1] >= 0.0)) return "inlet densities must be >= 0";
+    }
+    if (c->has_outlet) {
+        const lbm_outlet &o = c->outlet;
+        if (o.axis < 0 || o.axis >= c->dim || (o.side != 0 && o.side != 1)) return "bad outlet face";
+        if (c->periodic[o.axis]) return "outlet on a periodic axis";
+    }
+    const int64_t N = (int64_t)c->n[0] * c->n[1] * nz;
+    const int Q = lat_Q(c->dim);
+    m.type.assign(N, 0);
+    m.bslot.assign(N, -1);
+    m.in.clear();
+    m.out.clear();
+    auto solid_at = [&](const int *p) -> bool {
+        int q[3] = {p[0], p[1], p[2]};
+        for (int a = 0; a < c->dim; a++) {
+            const int n = c->n[a];
+            if (q[a] < 0) q[a] = c->periodic[a] ? q[a] + n : -1 - q[a];
+            else if (q[a] >= n) q[a] = c->periodic[a] ? q[a] - n : 2 * n - 1 - q[a];
+        }
+        return c->solid[(int64_t)q[0] + (int64_t)c->n[0] * ((int64_t)q[1] + (int64_t)c->n[1] * q[2])] != 0;
+    };
+    std::vector<int8_t> inlet_of(N, -1);
+    std::vector<uint8_t> is_out(N, 0);
+    for (int64_t b = 0; b < N; b++) {
+        if (c->solid[b]) continue;
+        const int xc[3] = {(int)(b % c->n[0]), (int)((b / c->n[0]) % c->n[1]), (int)(b / ((int64_t)c->n[0] * c->n[1]))};
+        for (int q = 0; q < c->n_inlets; q++)
+            if (on_face(c, xc, c->inlets[q].axis, c->inlets[q].side, c->inlets[q].lo, c->inlets[q].hi))
+                inlet_of[b] = (int8_t)q;
+        if (c->has_outlet && on_face(c, xc, c->outlet.axis, c->outlet.side, c->outlet.lo, c->outlet.hi))
+            is_out[b] = 1;
+        if (inlet_of[b] >= 0 && is_out[b]) return "a node belongs to an inlet and the outlet";
+    }
+    for (int64_t b = 0; b < N; b++) {
+        const int xc[3] = {(int)(b % c->n[0]), (int)((b / c->n[0]) % c->n[1]), (int)(b / ((int64_t)c->n[0] * c->n[1]))};
+        if (c->solid[b]) {
+            m.type[b] = T_SOLID;
+            continue;
+        }
+        uint32_t tw = 0;
+        for (int a = 0; a < c->dim; a++)
+            if (c->periodic[a] && (xc[a] == 0 || xc[a] == c->n[a] - 1)) tw |= T_EDGE;
+        for (int i = 0; i < Q; i++) {
+            int e[3];
+            dir(c->dim, i, e);
+            int s[3] = {xc[0] - e[0], xc[1] - e[1], xc[2] - e[2]};
+            bool outside = false;
+            for (int a = 0; a < c->dim; a++) {
+                if (s[a] < 0 || s[a] >= c->n[a]) {
+                    if (c->periodic[a]) s[a] = (s[a] + c->n[a]) % c->n[a];
+                    else outside = true;
+                }
+            }
+            if (outside) {
+                // the population arrives through a non-periodic face: an open
+                // boundary has to supply it
+                bool ok = false;
+                const int q = inlet_of[b];
+                if (q >= 0) ok = e[c->inlets[q].axis] * (c->inlets[q].side == 0 ? 1 : -1) > 0;
+                if (is_out[b]) ok = ok || e[c->outlet.axis] * (c->outlet.side == 0 ? -1 : 1) < 0;
+                if (!ok) return "a fluid node on a non-periodic face is not covered by an inlet or the outlet";
+                continue;
+            }
+            if (c->solid[(int64_t)s[0] + (int64_t)c->n[0] * ((int64_t)s[1] + (int64_t)c->n[1] * s[2])])
+                tw |= 1u << i;
+        }
+        const int zr = c->dim == 3 ? 2 : 0;
+        bool near = false;
+        for (int dz = -zr; dz <= zr && !near; dz++)
+            for (int dy = -2; dy <= 2 && !near; dy++)
+                for (int dx = -2; dx <= 2 && !near; dx++) {
+                    const int p[3] = {xc[0] + dx, xc[1] + dy, xc[2] + dz};
+                    if (solid_at(p)) near = true;
+                }
+        if (near) tw |= T_NEARWALL;
+        m.type[b] = tw;
+    }
+    // roles
+    for (int64_t b = 0; b < N; b++) {
+        const int q = inlet_of[b];
+        if (q < 0) continue;
+        const lbm_inlet &p = c->inlets[q];
+        const int xc[3] = {(int)(b % c->n[0]), (int)((b / c->n[0]) % c->n[1]), (int)(b / ((int64_t)c->n[0] * c->n[1]))};
+        int x2[3] = {xc[0], xc[1], xc[2]};
+        x2[p.axis] += p.side == 0 ? 1 : -1;
+        const int64_t b2 = (int64_t)x2[0] + (int64_t)c->n[0] * ((int64_t)x2[1] + (int64_t)c->n[1] * x2[2]);
+        m.type[b] |= T_INLET | ((uint32_t)q << T_PATCH_SHIFT);
+        if (!c->solid[b2]) {
+            if (m.type[b2] & T_INLET) return "inlet patches are less than two nodes apart";
+            m.type[b2] |= T_X2 | ((uint32_t)q << T_PATCH_SHIFT);
+        }
+        InletRec r{};
+        r.b1 = b;
+        r.b2 = b2;
+        r.patch = q;
+        m.in.push_back(r);
+    }
+    if (c->has_outlet) {
+        const lbm_outlet &o = c->outlet;
+        for (int64_t b = 0; b < N; b++) {
+            if (!is_out[b]) continue;
+            const int xc[3] = {(int)(b % c->n[0]), (int)((b / c->n[0]) % c->n[1]), (int)(b / ((int64_t)c->n[0] * c->n[1]))};
+            int xp[3] = {xc[0], xc[1], xc[2]};
+            xp[o.axis] += o.side == 0 ? 1 : -1;
+            const int64_t bp = (int64_t)xp[0] + (int64_t)c->n[0] * ((int64_t)xp[1] + (int64_t)c->n[1] * xp[2]);
+            m.type[b] |= T_OUTLET;
+            OutletRec r{};
+            r.bN = b;
+            r.bP = bp;
+            if (!c->solid[bp]) {
+                if (m.type[bp] & (T_INLET | T_OUTLET)) return "the outlet is less than two nodes from an open face";
+                m.type[bp] |= T_XPRIME;
+            } else {
+                r.bP = -1;
+            }
+            m.out.push_back(r);
+        }
+    }
+    int32_t slot = 0;
+    for (int64_t b = 0; b < N; b++)
+        if (m.type[b] & T_ROLE) m.bslot[b] = slot++;
+    for (auto &r : m.in) {
+        r.slot1 = m.bslot[r.b1];
+        r.slot2 = c->solid[r.b2] ? r.slot1 : m.bslot[r.b2];
+    }
+    for (auto &r : m.out) {
+        r.slotN = m.bslot[r.bN];
+        r.slotP = r.bP >= 0 ? m.bslot[r.bP] : -1;
+        if (r.bP < 0) r.bP = r.bN;
+    }
+    for (int64_t b = 0; b < N; b++) {
+        if (c->solid[b]) continue;
+        for (int k = 0; k < 2; k++)
+            if (!(c->rho0[k * N + b] > 0.0)) return "initial densities must be positive on fluid nodes";
+    }
+    return "";
+}
+
+Layout make_layout(const lbm_config *c, const Maps &m)
+{
+    Layout L;
+    L.dim = c->dim;
+    L.Q = lat_Q(c->dim);
+    L.storage = c->storage;
+    Geometry &g = L.g;
+    for (int a = 0; a < 3; a++) {
+        g.n[a] = a < c->dim ? c->n[a] : 1;
+        g.P[a] = a < c->dim ? c->n[a] + 2 : 1;
+        g.periodic[a] = a < c->dim ? (c->periodic[a] != 0) : 1;
+    }
+    g.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    g.Ppad = (int64_t)g.P[0] * g.P[1] * g.P[2];
+    if (c->dim == 2) {
+        L.tiles[0] = (g.n[0] + TX2 - 1) / TX2;
+        L.tiles[1] = (g.n[1] + TY2 - 1) / TY2;
+        L.tiles[2] = 1;
+    } else {
+        L.tiles[0] = (g.n[0] + TX3 - 1) / TX3;
+        L.tiles[1] = (g.n[1] + TY3 - 1) / TY3;
+        L.tiles[2] = (g.n[2] + TZ3 - 1) / TZ3;
+    }
+    L.nblocks_main = (int64_t)L.tiles[0] * L.tiles[1] * L.tiles[2];
+    L.n_in = (int64_t)m.in.size();
+    L.n_out = (int64_t)m.out.size();
+    L.n_slots = 0;
+    for (auto s : m.bslot) L.n_slots = std::max<int64_t>(L.n_slots, s + 1);
+    L.boundary = L.n_in > 0 || c->has_outlet;
+    L.nb_in = (int)((L.n_in + 255) / 256);
+    L.nb_out = (int)((L.n_out + 255) / 256);
+    L.nb_mass = (int)std::min<int64_t>(1024, (g.N + 255) / 256);
+    const size_t fbytes = (size_t)2 * L.Q * g.Ppad * (L.storage == LBM_STORE_F32 ? 4 : 2);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += align_up(std::max<size_t>(bytes, 1)); return at; };
+    L.o_fA = take(fbytes);
+    L.o_fB = take(fbytes);
+    L.o_type = take((size_t)g.N * 4);
+    L.o_bslot = take((size_t)g.N * 4);
+    L.o_faceF = take((size_t)L.n_slots * 6 * 4);
+    L.o_faceU = take((size_t)L.n_slots * 4);
+    L.o_in = take((size_t)L.n_in * sizeof(InletRec));
+    L.o_out = take((size_t)L.n_out * sizeof(OutletRec));
+    L.o_qpart = take((size_t)L.nblocks_main * 16);
+    L.o_ucpart = take((size_t)std::max(L.nb_out, 1) * 16);
+    L.o_scal = take(SC_COUNT * 8);
+    L.o_flag = take(4);
+    L.o_mpart = take((size_t)L.nb_mass * 16);
+    L.o_mout = take(16);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    Layout L;
+    lbm_config cfg;
+    Physics ph{};
+    Boundary bd{};
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    int cur = 0;           // which array holds f(t): 0 = A, 1 = B
+    int64_t steps = 0;
+    double mass0[2] = {0, 0};
+    bool unstable = false;
+    std::string err;
+    void *fsrc() const { return ws + (cur == 0 ? L.o_fA : L.o_fB); }
+    void *fdst() const { return ws + (cur == 0 ? L.o_fB : L.o_fA); }
+    const uint32_t *type() const { return (const uint32_t *)(ws + L.o_type); }
+    int *flag() const { return (int *)(ws + L.o_flag); }
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx *c, lbm_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+#define HIPCHECK(ctx, call)                                                                      \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ctx, LBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+template <int DIM, int STORE> struct Launch {
+    using T = typename Codec<STORE>::T;
+    static constexpr int TX = DIM == 2 ? TX2 : TX3;
+    static constexpr int TY = DIM == 2 ? TY2 : TY3;
+    static constexpr int TZ = DIM == 2 ? 1 : TZ3;
+
+    static void main_kernel(lbm_ctx *c, int mode, double *orho, double *ou)
+    {
+        const Layout &L = c->L;
+        Boundary bd = c->bd;
+        if (mode == MODE_MOMENTS) bd.qpart = nullptr;
+        if (mode == MODE_STEP)
+            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_STEP, TX, TY, TZ>), dim3((unsigned)L.nblocks_main), dim3(256), 0,
+                               c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->ph, bd,
+                               L.tiles[0], L.tiles[1], orho, ou, c->flag());
+        else
+            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_MOMENTS, TX, TY, TZ>), dim3((unsigned)L.nblocks_main), dim3(256), 0,
+                               c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->ph, bd,
+                               L.tiles[0], L.tiles[1], orho, ou, c->flag());
+    }
+
+    // ev (optional): 8 events bracketing the four launches of the step
+    static void step(lbm_ctx *c, hipEvent_t *ev = nullptr)
+    {
+        const Layout &L = c->L;
+        if (ev) hipEventRecord(ev[0], c->stream);
+        main_kernel(c, MODE_STEP, nullptr, nullptr);
+        if (ev) hipEventRecord(ev[1], c->stream);
+        if (L.boundary) {
+            const unsigned nb = (unsigned)std::max(L.nb_out, 1);
+            if (ev) hipEventRecord(ev[2], c->stream);
+            hipLaunchKernelGGL((k_outlet<DIM, STORE>), dim3(nb), dim3(256), 0, c->stream, (const T *)c->fsrc(),
+                               (T *)c->fdst(), c->type(), L.g, c->ph, c->bd, c->flag());
+            if (ev) hipEventRecord(ev[3], c->stream);
+            if (L.nb_in + L.nb_out > 0) {
+                if (ev) hipEventRecord(ev[4], c->stream);
+                hipLaunchKernelGGL((k_inlet<DIM, STORE>), dim3((unsigned)(L.nb_in + L.nb_out)), dim3(256), 0,
+                                   c->stream, (T *)c->fdst(), c->type(), L.g, c->bd, L.nb_in);
+                if (ev) hipEventRecord(ev[5], c->stream);
+            }
+            if (L.nb_out > 0) {
+                if (ev) hipEventRecord(ev[6], c->stream);
+                hipLaunchKernelGGL((k_outlet_fill<DIM, STORE>), dim3((unsigned)L.nb_out), dim3(256), 0, c->stream,
+                                   (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->bd);
+                if (ev) hipEventRecord(ev[7], c->stream);
+            }
+        }
+        c->cur ^= 1;
+    }
+
+    static void scatter(lbm_ctx *c, const double *dev_f)
+    {
+        const Layout &L = c->L;
+        hipLaunchKernelGGL((k_scatter<DIM, STORE>), dim3((unsigned)((L.g.N + 255) / 256)), dim3(256), 0, c->stream,
+                           (T *)c->fsrc(), c->type(), L.g, dev_f);
+    }
+
+    static void gather_state(lbm_ctx *c, double *dev_f)
+    {
+        const Layout &L = c->L;
+        hipLaunchKernelGGL((k_gather_state<DIM, STORE>), dim3((unsigned)((L.g.N + 255) / 256)), dim3(256), 0,
+                           c->stream, (const T *)c->fsrc(), c->type(), L.g, dev_f);
+    }
+
+    static void mass(lbm_ctx *c, double *out)
+    {
+        const Layout &L = c->L;
+        double *part = (double *)(c->ws + L.o_mpart);
+        hipLaunchKernelGGL((k_mass<DIM, STORE>), dim3((unsigned)L.nb_mass), dim3(256), 0, c->stream,
+                           (const T *)c->fsrc(), c->type(), L.g, part);
+        hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, c->stream, (const double *)part, L.nb_mass, out);
+    }
+};
+
+template <typename F> void dispatch(const lbm_ctx *c, F &&f)
+{
+    if (c->L.dim == 2) {
+        if (c->L.storage == LBM_STORE_F32) f(Launch<2, 0>{});
+        else f(Launch<2, 1>{});
+    } else {
+        if (c->L.storage == LBM_STORE_F32) f(Launch<3, 0>{});
+        else f(Launch<3, 1>{});
+    }
+}
+
+lbm_status current_mass(lbm_ctx *c, double *mass)
+{
+    double *out = (double *)(c->ws + c->L.o_mout);
+    dispatch(c, [&](auto l) { decltype(l)::mass(c, out); });
+    HIPCHECK(c, hipGetLastError());
+    HIPCHECK(c, hipMemcpyAsync(mass, out, 16, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status check_flag(lbm_ctx *c)
+{
+    int flag = 0;
+    HIPCHECK(c, hipMemcpyAsync(&flag, c->flag(), 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (flag) c->unstable = true;
+    return c->unstable ? LBM_EUNSTABLE : LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_config *cfg)
+{
+    Maps m;
+    if (!build_maps(cfg, m).empty()) return 0;
+    return make_layout(cfg, m).total;
+}
+
+lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void *hip_stream, lbm_ctx **out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    Maps m;
+    const std::string why = build_maps(cfg, m);
+    if (!why.empty()) return fail(nullptr, LBM_EINVAL, why);
+    Layout L = make_layout(cfg, m);
+    if (!dev_ws) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)dev_ws) % ALIGN) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(nullptr, LBM_ENOMEM, "workspace too small");
+
+    lbm_ctx *c = new lbm_ctx();
+    c->L = L;
+    c->cfg = *cfg;
+    c->cfg.solid = nullptr;
+    c->cfg.rho0 = nullptr;
+    c->cfg.u0 = nullptr;
+    c->ws = (char *)dev_ws;
+    c->stream = (hipStream_t)hip_stream;
+
+    // relaxation rates (eqs. 4-5, Sec. III A)
+    Physics &ph = c->ph;
+    const double numax = std::max(cfg->nu[0], cfg->nu[1]);
+    for (int k = 0; k < 2; k++) {
+        const double snu = 1.0 / (3.0 * cfg->nu[k] + 0.5);
+        const double seps = cfg->s_eps_policy == LBM_SEPS_MAXVISC ? 1.0 / (3.0 * numax + 0.5) : snu;
+        ph.snu[k] = (float)snu;
+        ph.seps[k] = (float)seps;
+        ph.se[k] = (float)seps;
+    }
+    ph.sq = (float)cfg->s_q;
+    ph.G12 = (float)cfg->G12;
+    ph.Gw[0] = (float)cfg->Gw[0];
+    ph.Gw[1] = (float)cfg->Gw[1];
+    for (int d = 0; d < 3; d++) ph.Fb[d] = (float)cfg->Fb[d];
+    ph.adhesion = (cfg->Gw[0] != 0.0 || cfg->Gw[1] != 0.0) ? 1 : 0;
+
+    Boundary &bd = c->bd;
+    bd.n_patch = cfg->n_inlets;
+    for (int q = 0; q < cfg->n_inlets; q++) {
+        const lbm_inlet &p = cfg->inlets[q];
+        bd.patch[q].axis = p.axis;
+        bd.patch[q].sign = p.side == 0 ? 1 : -1;
+        bd.patch[q].rho[0] = (float)p.rho[0];
+        bd.patch[q].rho[1] = (float)p.rho[1];
+        bd.patch[q].u_n = (float)p.u_n;
+        bd.patch[q].alpha_on = p.alpha_on ? 1 : 0;
+    }
+    bd.has_outlet = cfg->has_outlet ? 1 : 0;
+    bd.chi_on = cfg->has_outlet && cfg->outlet.chi_on ? 1 : 0;
+    bd.out_axis = cfg->has_outlet ? cfg->outlet.axis : 0;
+    bd.out_sign = cfg->has_outlet ? (cfg->outlet.side == 0 ? -1 : 1) : 1;
+    bd.n_in = (int)L.n_in;
+    bd.n_out = (int)L.n_out;
+    char *ws = c->ws;
+    bd.in = (const InletRec *)(ws + L.o_in);
+    bd.out = (const OutletRec *)(ws + L.o_out);
+    bd.bslot = (const int *)(ws + L.o_bslot);
+    bd.faceF = (float *)(ws + L.o_faceF);
+    bd.faceU = (float *)(ws + L.o_faceU);
+    bd.qpart = L.boundary ? (double *)(ws + L.o_qpart) : nullptr;
+    bd.n_qpart = (int)L.nblocks_main;
+    bd.ucpart = (double *)(ws + L.o_ucpart);
+    bd.n_ucpart = L.nb_out;
+    bd.scal = (double *)(ws + L.o_scal);
+
+    auto st = [&]() -> lbm_status {
+        hipStream_t s = c->stream;
+        HIPCHECK(c, hipMemsetAsync(ws, 0, L.total, s));
+        HIPCHECK(c, hipMemcpyAsync(ws + L.o_type, m.type.data(), m.type.size() * 4, hipMemcpyHostToDevice, s));
+        HIPCHECK(c, hipMemcpyAsync(ws + L.o_bslot, m.bslot.data(), m.bslot.size() * 4, hipMemcpyHostToDevice, s));
+        if (L.n_in)
+            HIPCHECK(c, hipMemcpyAsync(ws + L.o_in, m.in.data(), m.in.size() * sizeof(InletRec), hipMemcpyHostToDevice, s));
+        if (L.n_out)
+            HIPCHECK(c, hipMemcpyAsync(ws + L.o_out, m.out.data(), m.out.size() * sizeof(OutletRec), hipMemcpyHostToDevice, s));
+        const double one = 1.0;
+        HIPCHECK(c, hipMemcpyAsync(ws + L.o_scal + SC_CHI * 8, &one, 8, hipMemcpyHostToDevice, s));
+        // initial state f = feq(rho0, u0), scattered into the source slots
+        const int64_t N = L.g.N;
+        double *d_rho = nullptr, *d_u = nullptr, *d_f = nullptr;
+        HIPCHECK(c, hipMalloc(&d_rho, (size_t)2 * N * 8));
+        if (cfg->u0) HIPCHECK(c, hipMalloc(&d_u, (size_t)3 * N * 8));
+        HIPCHECK(c, hipMalloc(&d_f, (size_t)2 * L.Q * N * 8));
+        HIPCHECK(c, hipMemcpyAsync(d_rho, cfg->rho0, (size_t)2 * N * 8, hipMemcpyHostToDevice, s));
+        if (cfg->u0) HIPCHECK(c, hipMemcpyAsync(d_u, cfg->u0, (size_t)3 * N * 8, hipMemcpyHostToDevice, s));
+        if (L.dim == 2)
+            hipLaunchKernelGGL(k_feq_state<2>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                               (const double *)d_rho, (const double *)d_u, N, d_f);
+        else
+            hipLaunchKernelGGL(k_feq_state<3>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
+                               (const double *)d_rho, (const double *)d_u, N, d_f);
+        dispatch(c, [&](auto l) { decltype(l)::scatter(c, d_f); });
+        HIPCHECK(c, hipGetLastError());
+        HIPCHECK(c, hipStreamSynchronize(s));
+        HIPCHECK(c, hipFree(d_rho));
+        if (d_u) HIPCHECK(c, hipFree(d_u));
+        HIPCHECK(c, hipFree(d_f));
+        return current_mass(c, c->mass0);
+    }();
+    if (st != LBM_OK) {
+        g_create_error = c->err;
+        delete c;
+        return st;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t n)
+{
+    if (!c || n < 0) return fail(c, LBM_EINVAL, "bad arguments to lbm_step");
+    if (c->unstable) return fail(c, LBM_ESTATE, "context flagged unstable");
+    for (int64_t t = 0; t < n; t++) dispatch(c, [&](auto l) { decltype(l)::step(c); });
+    HIPCHECK(c, hipGetLastError());
+    c->steps += n;
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx *c, double *rho, double *u, int dst_on_device)
+{
+    if (!c || !rho || !u) return fail(c, LBM_EINVAL, "bad arguments to lbm_moments");
+    const int64_t N = c->L.g.N;
+    double *drho = rho, *du = u;
+    if (!dst_on_device) {
+        HIPCHECK(c, hipMalloc(&drho, (size_t)2 * N * 8));
+        HIPCHECK(c, hipMalloc(&du, (size_t)3 * N * 8));
+    }
+    HIPCHECK(c, hipMemsetAsync(du, 0, (size_t)3 * N * 8, c->stream));
+    dispatch(c, [&](auto l) { decltype(l)::main_kernel(c, MODE_MOMENTS, drho, du); });
+    HIPCHECK(c, hipGetLastError());
+    if (!dst_on_device) {
+        HIPCHECK(c, hipMemcpyAsync(rho, drho, (size_t)2 * N * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(u, du, (size_t)3 * N * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (!dst_on_device) {
+        HIPCHECK(c, hipFree(drho));
+        HIPCHECK(c, hipFree(du));
+    }
+    return check_flag(c);
+}
+
+lbm_status lbm_mass_flux(lbm_ctx *c, lbm_flux *out)
+{
+    if (!c || !out) return fail(c, LBM_EINVAL, "bad arguments to lbm_mass_flux");
+    double sc[SC_COUNT];
+    HIPCHECK(c, hipMemcpyAsync(sc, c->ws + c->L.o_scal, sizeof sc, hipMemcpyDeviceToHost, c->stream));
+    double mass[2];
+    lbm_status st = current_mass(c, mass);
+    if (st != LBM_OK) return st;
+    out->step = c->steps;
+    out->q_in = sc[SC_QIN];
+    out->q_out = sc[SC_QOUT];
+    out->chi = sc[SC_CHI];
+    out->u_conv = sc[SC_UC];
+    out->uc_clamps = (int64_t)sc[SC_CLAMPS];
+    out->mass[0] = mass[0];
+    out->mass[1] = mass[1];
+    out->mass0[0] = c->mass0[0];
+    out->mass0[1] = c->mass0[1];
+    return check_flag(c);
+}
+
+lbm_status lbm_get_state(lbm_ctx *c, double *f_host, size_t bytes)
+{
+    if (!c || !f_host) return fail(c, LBM_EINVAL, "bad arguments to lbm_get_state");
+    const size_t need = (size_t)16 * c->L.Q * c->L.g.N;
+    if (bytes != need) return fail(c, LBM_EINVAL, "state buffer has the wrong size");
+    double *d = nullptr;
+    HIPCHECK(c, hipMalloc(&d, need));
+    dispatch(c, [&](auto l) { decltype(l)::gather_state(c, d); });
+    HIPCHECK(c, hipGetLastError());
+    HIPCHECK(c, hipMemcpyAsync(f_host, d, need, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipFree(d));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx *c, const double *f_host, size_t bytes)
+{
+    if (!c || !f_host) return fail(c, LBM_EINVAL, "bad arguments to lbm_set_state");
+    const size_t need = (size_t)16 * c->L.Q * c->L.g.N;
+    if (bytes != need) return fail(c, LBM_EINVAL, "state buffer has the wrong size");
+    double *d = nullptr;
+    HIPCHECK(c, hipMalloc(&d, need));
+    HIPCHECK(c, hipMemcpyAsync(d, f_host, need, hipMemcpyHostToDevice, c->stream));
+    dispatch(c, [&](auto l) { decltype(l)::scatter(c, d); });
+    HIPCHECK(c, hipGetLastError());
+    HIPCHECK(c, hipMemsetAsync(c->flag(), 0, 4, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    HIPCHECK(c, hipFree(d));
+    c->unstable = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_time_kernels(lbm_ctx *c, int64_t n, double *ms)
+{
+    if (!c || n <= 0 || !ms) return fail(c, LBM_EINVAL, "bad arguments to lbm_time_kernels");
+    if (c->unstable) return fail(c, LBM_ESTATE, "context flagged unstable");
+    const int64_t total = n * 8;
+    std::vector<hipEvent_t> ev(total);
+    for (auto &e : ev) HIPCHECK(c, hipEventCreate(&e));
+    for (int64_t t = 0; t < n; t++) dispatch(c, [&](auto l) { decltype(l)::step(c, ev.data() + 8 * t); });
+    HIPCHECK(c, hipGetLastError());
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->steps += n;
+    const bool used[4] = {true, c->L.boundary, c->L.boundary && c->L.nb_in + c->L.nb_out > 0,
+                          c->L.boundary && c->L.nb_out > 0};
+    for (int k = 0; k < 4; k++) {
+        double acc = 0.0;
+        if (used[k])
+            for (int64_t t = 0; t < n; t++) {
+                float v = 0.0f;
+                HIPCHECK(c, hipEventElapsedTime(&v, ev[8 * t + 2 * k], ev[8 * t + 2 * k + 1]));
+                acc += v;
+            }
+        ms[k] = used[k] ? acc / (double)n : 0.0;
+    }
+    for (auto &e : ev) HIPCHECK(c, hipEventDestroy(e));
+    return LBM_OK;
+}
+
+int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
+
+void lbm_destroy(lbm_ctx *c) { delete c; }
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+"""Thin ctypes binding of the C ABI in ``include/lbm.h``.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``liblbm.so``.  PyTorch provides the device workspace and the stream.  If
+the library is missing the constructor raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = range(6)
+STATUS = {0: "LBM_OK", 1: "LBM_EINVAL", 2: "LBM_ENOMEM", 3: "LBM_EDEVICE", 4: "LBM_EUNSTABLE", 5: "LBM_ESTATE"}
+STORE = {"f32": 0, "f16": 1}
+MAX_INLETS = 8
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Inlet(C.Structure):
+    _fields_ = [("axis", C.c_int), ("side", C.c_int), ("lo", C.c_int * 3), ("hi", C.c_int * 3),
+                ("rho", C.c_double * 2), ("u_n", C.c_double), ("alpha_on", C.c_int)]
+
+
+class Outlet(C.Structure):
+    _fields_ = [("axis", C.c_int), ("side", C.c_int), ("lo", C.c_int * 3), ("hi", C.c_int * 3),
+                ("chi_on", C.c_int)]
+
+
+class Config(C.Structure):
+    _fields_ = [("dim", C.c_int), ("storage", C.c_int), ("n", C.c_int * 3), ("periodic", C.c_int * 3),
+                ("nu", C.c_double * 2), ("s_q", C.c_double), ("s_eps_policy", C.c_int),
+                ("G12", C.c_double), ("Gw", C.c_double * 2), ("Fb", C.c_double * 3),
+                ("n_inlets", C.c_int), ("inlets", Inlet * MAX_INLETS), ("has_outlet", C.c_int),
+                ("outlet", Outlet), ("solid", C.c_void_p), ("rho0", C.c_void_p), ("u0", C.c_void_p)]
+
+
+class Flux(C.Structure):
+    _fields_ = [("step", C.c_int64), ("q_in", C.c_double), ("q_out", C.c_double), ("chi", C.c_double),
+                ("u_conv", C.c_double), ("mass", C.c_double * 2), ("mass0", C.c_double * 2),
+                ("uc_clamps", C.c_int64)]
+
+    def as_dict(self):
+        return {"step": self.step, "q_in": self.q_in, "q_out": self.q_out, "chi": self.chi,
+                "u_conv": self.u_conv, "mass": [self.mass[0], self.mass[1]],
+                "mass0": [self.mass0[0], self.mass0[1]], "uc_clamps": self.uc_clamps}
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbm.so (torch is imported first so that both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads the HIP runtime the workspace comes from)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        cp, vp, dp = C.POINTER(Config), C.c_void_p, C.POINTER(C.c_double)
+        L.lbm_workspace_bytes.argtypes = [cp]
+        L.lbm_workspace_bytes.restype = C.c_size_t
+        L.lbm_create.argtypes = [cp, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_step.argtypes = [vp, C.c_int64]
+        L.lbm_moments.argtypes = [vp, vp, vp, C.c_int]
+        L.lbm_mass_flux.argtypes = [vp, C.POINTER(Flux)]
+        L.lbm_get_state.argtypes = [vp, vp, C.c_size_t]
+        L.lbm_set_state.argtypes = [vp, vp, C.c_size_t]
+        L.lbm_time_kernels.argtypes = [vp, C.c_int64, C.POINTER(C.c_double)]
+        L.lbm_time_kernels.restype = C.c_int
+        L.lbm_steps_done.argtypes = [vp]
+        L.lbm_steps_done.restype = C.c_int64
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_destroy.restype = None
+        L.lbm_last_error.argtypes = [vp]
+        L.lbm_last_error.restype = C.c_char_p
+        for name in ("lbm_create", "lbm_step", "lbm_moments", "lbm_mass_flux", "lbm_get_state", "lbm_set_state"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def make_config(case, storage="f32"):
+    """Fill an ``lbm_config`` from a case; returns (config, arrays kept alive)."""
+    cfg = Config()
+    cfg.dim = case.dim
+    cfg.storage = STORE[storage]
+    for a in range(3):
+        cfg.n[a] = int(case.n[a])
+        cfg.periodic[a] = int(bool(case.periodic[a]))
+    cfg.nu[0], cfg.nu[1] = case.nu
+    cfg.s_q = case.s_q
+    cfg.s_eps_policy = int(case.s_eps_policy)
+    cfg.G12 = case.G12
+    cfg.Gw[0], cfg.Gw[1] = case.Gw
+    for a in range(3):
+        cfg.Fb[a] = case.Fb[a]
+    if len(case.inlets) > MAX_INLETS:
+        raise ValueError("too many inlet patches")
+    cfg.n_inlets = len(case.inlets)
+    for j, inl in enumerate(case.inlets):
+        q = cfg.inlets[j]
+        q.axis, q.side = inl["axis"], inl["side"]
+        for a in range(3):
+            q.lo[a], q.hi[a] = inl["lo"][a], inl["hi"][a]
+        q.rho[0], q.rho[1] = inl["rho"]
+        q.u_n = inl["u_n"]
+        q.alpha_on = int(inl.get("alpha_on", 1))
+    if case.outlet is not None:
+        o = case.outlet
+        cfg.has_outlet = 1
+        cfg.outlet.axis, cfg.outlet.side = o["axis"], o["side"]
+        for a in range(3):
+            cfg.outlet.lo[a], cfg.outlet.hi[a] = o["lo"][a], o["hi"][a]
+        cfg.outlet.chi_on = int(o.get("chi_on", 1))
+    solid = np.ascontiguousarray(case.solid, dtype=np.uint8).reshape(-1)
+    rho0 = np.ascontiguousarray(case.rho0, dtype=np.float64).reshape(-1)
+    u0 = None if case.u0 is None else np.ascontiguousarray(case.u0, dtype=np.float64).reshape(-1)
+    cfg.solid = solid.ctypes.data
+    cfg.rho0 = rho0.ctypes.data
+    cfg.u0 = None if u0 is None else u0.ctypes.data
+    return cfg, (solid, rho0, u0)
+
+
+def workspace_bytes(case, storage="f32"):
+    cfg, keep = make_config(case, storage)
+    return int(lib().lbm_workspace_bytes(C.byref(cfg)))
+
+
+class LBM:
+    """One simulation context on a GPU (device memory from torch)."""
+
+    def __init__(self, case, storage="f32", device="cuda:0", stream=None):
+        import torch
+        L = lib()
+        self.case = case
+        self.dim = case.dim
+        self.Q = 9 if case.dim == 2 else 19
+        self.N = int(np.prod(case.n))
+        self.device = torch.device(device)
+        cfg, keep = make_config(case, storage)
+        nbytes = int(L.lbm_workspace_bytes(C.byref(cfg)))
+        if nbytes == 0:
+            h = C.c_void_p()
+            st = L.lbm_create(C.byref(cfg), None, 0, None, C.byref(h))
+            raise LBMError(st, L.lbm_last_error(None).decode())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = L.lbm_create(C.byref(cfg), C.c_void_p(self.ws.data_ptr()), nbytes,
+                          C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != LBM_OK:
+            raise LBMError(st, L.lbm_last_error(None).decode())
+        self._h = h
+        self.workspace_bytes = nbytes
+
+    def _check(self, st):
+        if st != LBM_OK:
+            raise LBMError(st, lib().lbm_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        self._check(lib().lbm_step(self._h, int(n)))
+
+    def moments(self, check=True):
+        """Return (rho [2,N], u [3,N]) as float64 numpy arrays."""
+        rho = np.zeros((2, self.N))
+        u = np.zeros((3, self.N))
+        st = lib().lbm_moments(self._h, rho.ctypes.data, u.ctypes.data, 0)
+        if check:
+            self._check(st)
+        return rho, u
+
+    def moments_device(self, rho, u):
+        """Write moments into caller-owned float64 CUDA tensors [2,N] and [3,N]."""
+        return lib().lbm_moments(self._h, rho.data_ptr(), u.data_ptr(), 1)
+
+    def mass_flux(self, check=True):
+        out = Flux()
+        st = lib().lbm_mass_flux(self._h, C.byref(out))
+        if check:
+            self._check(st)
+        return out.as_dict()
+
+    def get_state(self):
+        f = np.zeros((2, self.Q, self.N))
+        self._check(lib().lbm_get_state(self._h, f.ctypes.data, f.nbytes))
+        return f
+
+    def set_state(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (2, self.Q, self.N)
+        self._check(lib().lbm_set_state(self._h, f.ctypes.data, f.nbytes))
+
+    def time_kernels(self, n):
+        """Run n steps with HIP events around every launch; mean ms of
+        (node update, outlet collision, inlet reconstruction, outlet fill)."""
+        ms = (C.c_double * 4)()
+        self._check(lib().lbm_time_kernels(self._h, int(n), ms))
+        return list(ms)
+
+    @property
+    def steps(self):
+        return int(lib().lbm_steps_done(self._h))

@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every entry point of include/lbm.h;
+configuration validation (pure host code) answers without a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:lbm_status|size_t|void|int64_t|const char \*)\s*\*?\s*(lbm_\w+)\s*\(",
+                                 src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2512_12934_amd import build
+    if build.stale():
+        build.build()
+    from paper_2512_12934_amd import lbm
+    return lbm.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_workspace_bytes_validates(lib):
+    from paper_2512_12934_amd import cases, lbm
+    c = cases.tjunction(W=20, length=90, x_side=30, side_width=14, side_len=18)
+    ws = lbm.workspace_bytes(c)
+    assert ws > 2 * 2 * 9 * c.N * 4
+    assert lbm.workspace_bytes(c, "f16") < ws
+    bad = c.copy(nu=(0.1, -1.0))
+    assert lbm.workspace_bytes(bad) == 0
+    # an open face not covered by a patch
+    bad = c.copy(outlet=None)
+    assert lbm.workspace_bytes(bad) == 0
+    # a 2-node axis
+    small = cases.random_box((8, 2), seed=0)
+    assert lbm.workspace_bytes(small) == 0
+
+
+def test_create_rejects_invalid_config_before_any_device_work(lib):
+    from paper_2512_12934_amd import cases, lbm
+    c = cases.laplace(n=16, R=4).copy(nu=(0.0, 0.1))
+    cfg, keep = lbm.make_config(c)
+    h = C.c_void_p()
+    st = lib.lbm_create(C.byref(cfg), None, 0, None, C.byref(h))
+    assert st == lbm.LBM_EINVAL
+    assert b"viscosities" in lib.lbm_last_error(None)
+    assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL

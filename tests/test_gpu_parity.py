@@ -1,0 +1,154 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances.  The GPU computes in FP32 (unit roundoff 6e-8).  The collision
+passes every population through the moment transform, whose moments reach
+about 30 rho and whose rows are summed over Q = 9 or 19 entries, so one step
+carries an absolute error of order Q * 30 * 6e-8 * rho ~ 1e-5 rho per
+population at worst.  States are therefore compared element by element as
+max |f_gpu - f_oracle| / (rho_1 + rho_2) at the node: 1e-5 after one step,
+1e-4 after 20 steps.  After 1000 steps the fields are compared with the 1e-4 bound on
+max|rho_gpu - rho_oracle| / max|rho_oracle|; velocities with the same bound
+relative to the largest velocity of the oracle field plus an absolute floor of
+2e-7 (the FP32 resolution of the momentum sum at unit density).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_12934_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(case, storage="f32"):
+    from paper_2512_12934_amd.lbm import LBM
+    print(f"[gpu] {case.name} n={case.n} storage={storage}", flush=True)
+    return LBM(case, storage=storage)
+
+
+def _rel(a, b, floor=0.0):
+    return np.abs(a - b).max() / max(np.abs(b).max(), floor)
+
+
+def _compare_state(g, s, tol=None):
+    """max |f_gpu - f_oracle| over populations, relative to the node density."""
+    fg = g.get_state()
+    fo = s.get_f()
+    fluid = g.case.solid == 0
+    scale = fo[:, :, fluid].sum(axis=(0, 1))
+    err = np.abs(fg[:, :, fluid] - fo[:, :, fluid]) / scale
+    assert np.isfinite(fg[:, :, fluid]).all()
+    return err.max()
+
+
+def _compare_fields(g, s, tol_rho, tol_u, u_floor=2e-7):
+    rg, ug = g.moments()
+    ro, uo, _ = s.moments()
+    fluid = g.case.solid == 0
+    er = _rel(rg[:, fluid], ro[:, fluid])
+    eu = np.abs(ug[:, fluid] - uo[:, fluid]).max() / max(np.abs(uo[:, fluid]).max(), 1e-30)
+    abs_u = np.abs(ug[:, fluid] - uo[:, fluid]).max()
+    print(f"  rho rel err {er:.3e}  u rel err {eu:.3e} (abs {abs_u:.3e})", flush=True)
+    assert er < tol_rho
+    assert eu < tol_u or abs_u < u_floor
+    return er, eu
+
+
+SMALL = [
+    ("random2d", lambda: cases.random_box((70, 20), seed=1, u_amp=0.01)),
+    ("random2d_walls", lambda: cases.random_box((70, 21), seed=2, periodic=(False, False, True), walls=True,
+                                                Gw=(0.05, -0.05), Fb=(1e-5, -2e-5, 0.0), u_amp=0.01)),
+    ("random3d", lambda: cases.random_box((36, 10, 9), seed=3, dim=3, u_amp=0.01)),
+    ("random3d_walls", lambda: cases.random_box((34, 11, 10), seed=4, dim=3, periodic=(False, True, False),
+                                                walls=True, Gw=(0.05, -0.05), u_amp=0.01)),
+    ("tjunction_small", lambda: cases.tjunction(W=20, length=90, x_side=30, side_width=14, side_len=18)),
+    ("coflow_small", lambda: cases.coflow3d(length=40, width=10, inner=4)),
+    ("channel_nochi", lambda: cases.channel(70, 12, 0.01, droplet=(50, 7, 4), chi_on=False, alpha_on=False)),
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL, ids=[s[0] for s in SMALL])
+def test_one_step_parity(name, make):
+    c = make()
+    g = _gpu(c)
+    s = oracle.Sim(c)
+    # the initial states agree (feq evaluated in FP32 on the device: a few ulp)
+    assert _compare_state(g, s) < 1e-6
+    g.step(1)
+    s.step(1)
+    err = _compare_state(g, s)
+    print(f"  one-step max err on f / rho: {err:.3e}", flush=True)
+    assert err < 1e-5
+    g.step(19)
+    s.step(19)
+    err = _compare_state(g, s)
+    print(f"  20-step max err on f / rho: {err:.3e}", flush=True)
+    assert err < 1e-4
+    dg, do = g.mass_flux(), s.diag()
+    for key in ("q_in", "q_out", "chi", "u_conv"):
+        assert abs(dg[key] - do[key]) <= 1e-5 * max(1.0, abs(do[key])), key
+
+
+@pytest.mark.parametrize("name,make", [
+    ("laplace_64", lambda: cases.laplace()),
+    ("tjunction_800x100", lambda: cases.tjunction()),
+])
+def test_fields_step_1000(name, make):
+    """FP32 fields within 1e-4 relative of the FP64 oracle at step 1000."""
+    c = make()
+    g = _gpu(c)
+    s = oracle.Sim(c)
+    g.step(1000)
+    s.step(1000)
+    _compare_fields(g, s, 1e-4, 1e-4)
+    dg, do = g.mass_flux(), s.diag()
+    print("  gpu", dg, "\n  oracle", do, flush=True)
+    for k in range(2):
+        assert abs(dg["mass"][k] - do["mass"][k]) < 1e-5 * do["mass"][k]
+
+
+def test_coflow_quarter_step_1000():
+    """The 1/4-scale co-flow device (150 x 30 x 30 fluid, D3Q19) at step 1000."""
+    c = cases.coflow3d_quarter()
+    g = _gpu(c)
+    s = oracle.Sim(c)
+    g.step(1000)
+    s.step(1000)
+    _compare_fields(g, s, 1e-4, 1e-4)
+
+
+def test_checkpoint_restart_bitwise():
+    c = cases.tjunction(W=20, length=90, x_side=30, side_width=14, side_len=18)
+    a = _gpu(c)
+    a.step(50)
+    f = a.get_state()
+    b = _gpu(c)
+    b.set_state(f)
+    a.step(30)
+    b.step(30)
+    assert np.array_equal(a.get_state(), b.get_state())
+
+
+def test_determinism_bitwise():
+    c = cases.coflow3d(length=40, width=10, inner=4)
+    a, b = _gpu(c), _gpu(c)
+    a.step(40)
+    b.step(40)
+    assert np.array_equal(a.get_state(), b.get_state())
+    assert a.mass_flux() == b.mass_flux()
+
+
+def test_unstable_flag():
+    from paper_2512_12934_amd.lbm import LBMError, LBM_EUNSTABLE, LBM_ESTATE
+    c = cases.random_box((40, 16), seed=5)
+    g = _gpu(c)
+    f = g.get_state()
+    f[0, 3, 100] = np.nan
+    g.set_state(f)
+    g.step(1)
+    with pytest.raises(LBMError) as e:
+        g.moments()
+    assert e.value.status == LBM_EUNSTABLE
+    with pytest.raises(LBMError) as e:
+        g.step(1)
+    assert e.value.status == LBM_ESTATE
