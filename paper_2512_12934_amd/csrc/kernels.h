@@ -10,11 +10,12 @@
 // Two arrays alternate between source and destination every step.
 //
 // One step is four launches:
-//   k_main           all fluid nodes: densities of the tile plus a two-node
-//                    halo into LDS (mirror ghost layers at open faces,
-//                    eqs. 24-25), force (eqs. 10-11), common velocity
-//                    (eqs. 7-8), MRT collision (eq. 1); FP64 partial mass
-//                    flows at inlet nodes and the x_{N-1} column (eq. 23)
+//   k_main           all fluid nodes, swept along the last axis: densities of
+//                    each plane plus a two-node lateral halo into an LDS ring
+//                    (mirror ghost layers at open faces, eqs. 24-25), force
+//                    (eqs. 10-11), common velocity (eqs. 7-8), MRT collision
+//                    (eq. 1); FP64 partial mass flows at inlet nodes and the
+//                    x_{N-1} column (eq. 23)
 //   k_outlet         chi = Q_in / Q' (eq. 23) and the collision of the outlet
 //                    column with the corrected normal velocity (eq. 22)
 //   k_inlet          alpha-corrected NEQ extrapolation (eqs. 13-19) into the
@@ -45,6 +46,52 @@ template <> struct Codec<1> {
     static __device__ __forceinline__ void st(T *p, float v, float w) { *p = __float2half_rn(v - w); }
 };
 
+// Raw buffer access for the node update: one descriptor per component array
+// (range-checked by the hardware), a 32-bit per-lane byte offset and a
+// wave-uniform byte offset per population plane.
+constexpr int BUF_FLAGS = 0x00020000;   // dword 3 of a raw gfx9 buffer descriptor
+
+template <int STORE> struct Buf;
+template <> struct Buf<0> {
+    static constexpr uint32_t SZ = 4;
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float)
+    {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, so, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, so, 0);
+    }
+};
+template <> struct Buf<1> {
+    static constexpr uint32_t SZ = 2;
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w)
+    {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, so, 0);
+        return __half2float(__ushort_as_half(h)) + w;
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v - w)), r, (int)vo, so, 0);
+    }
+};
+
+template <int STORE>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t comp_rsrc(const void *base, int comp, int Q, int64_t Ppad)
+{
+    const char *p = (const char *)base + (int64_t)comp * Q * Ppad * Buf<STORE>::SZ;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)((int64_t)Q * Ppad * Buf<STORE>::SZ),
+                                             BUF_FLAGS);
+}
+
+__device__ __forceinline__ float pick3(const float (&v)[3], int a) { return a == 0 ? v[0] : (a == 1 ? v[1] : v[2]); }
+
+template <int DIM>
+__device__ __forceinline__ int e_axis(int i, int a)
+{
+    return a == 0 ? Lat<DIM>::E[i][0] : (a == 1 ? Lat<DIM>::E[i][1] : Lat<DIM>::E[i][2]);
+}
+
 __device__ __forceinline__ int64_t pidx(const Geometry &g, int x, int y, int z)
 {
     return (int64_t)(x + 1) + (int64_t)g.P[0] * ((int64_t)(y + 1) + (int64_t)g.P[1] * (int64_t)(z + 1));
@@ -62,53 +109,63 @@ __device__ __forceinline__ int64_t dir_off(const Geometry &g, int i)
 template <int DIM>
 __device__ __forceinline__ int64_t src_slot(const Geometry &g, int x, int y, int z, int i)
 {
-    int s[3] = {x - Lat<DIM>::E[i][0], y - Lat<DIM>::E[i][1], z - Lat<DIM>::E[i][2]};
-#pragma unroll
-    for (int a = 0; a < DIM; a++) {
-        if (g.periodic[a]) {
-            if (s[a] < 0) s[a] += g.n[a];
-            else if (s[a] >= g.n[a]) s[a] -= g.n[a];
-        }
-    }
-    if (DIM == 2) s[2] = -1;
-    return pidx(g, s[0], s[1], s[2]);
+    int s0 = x - Lat<DIM>::E[i][0], s1 = y - Lat<DIM>::E[i][1], s2 = z - Lat<DIM>::E[i][2];
+    if (g.periodic[0]) s0 = s0 < 0 ? s0 + g.n[0] : (s0 >= g.n[0] ? s0 - g.n[0] : s0);
+    if (g.periodic[1]) s1 = s1 < 0 ? s1 + g.n[1] : (s1 >= g.n[1] ? s1 - g.n[1] : s1);
+    if (DIM == 3 && g.periodic[2]) s2 = s2 < 0 ? s2 + g.n[2] : (s2 >= g.n[2] ? s2 - g.n[2] : s2);
+    if (DIM == 2) s2 = -1;
+    return pidx(g, s0, s1, s2);
 }
 
-// Post-streaming populations of one component at one node.
+// Slot index (padded, within one component array) supplying population i.
+template <int DIM>
+__device__ __forceinline__ int64_t slot_of(const Geometry &g, int64_t p, uint32_t tw, int x, int y, int z, int i)
+{
+    if ((tw >> i) & 1u) return (int64_t)Lat<DIM>::OPP[i] * g.Ppad + p;
+    return (int64_t)i * g.Ppad + ((tw & T_EDGE) ? src_slot<DIM>(g, x, y, z, i) : p - dir_off<DIM>(g, i));
+}
+
+// Post-streaming populations of one component at one node (pointer access).
 template <int DIM, int STORE>
 __device__ __forceinline__ void gather(const typename Codec<STORE>::T *__restrict__ fk, const Geometry &g,
                                        int64_t p, uint32_t tw, int x, int y, int z,
                                        float (&f)[Lat<DIM>::Q])
 {
-    constexpr int Q = Lat<DIM>::Q;
-    if (!(tw & T_EDGE)) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const bool bb = (tw >> i) & 1u;
-            const int64_t a = bb ? (int64_t)Lat<DIM>::OPP[i] * g.Ppad + p
-                                 : (int64_t)i * g.Ppad + p - dir_off<DIM>(g, i);
-            f[i] = Codec<STORE>::ld(fk + a, weight<DIM>(i));
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const bool bb = (tw >> i) & 1u;
-            const int64_t a = bb ? (int64_t)Lat<DIM>::OPP[i] * g.Ppad + p
-                                 : (int64_t)i * g.Ppad + src_slot<DIM>(g, x, y, z, i);
-            f[i] = Codec<STORE>::ld(fk + a, weight<DIM>(i));
-        }
-    }
+    static_for<Lat<DIM>::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        f[i] = Codec<STORE>::ld(fk + slot_of<DIM>(g, p, tw, x, y, z, i), weight<DIM>(i));
+    });
 }
 
-// Single post-streaming population i of one component.
 template <int DIM, int STORE>
 __device__ __forceinline__ float gather1(const typename Codec<STORE>::T *__restrict__ fk, const Geometry &g,
                                          int64_t p, uint32_t tw, int x, int y, int z, int i)
 {
-    const bool bb = (tw >> i) & 1u;
-    const int64_t a = bb ? (int64_t)Lat<DIM>::OPP[i] * g.Ppad + p
-                         : (int64_t)i * g.Ppad + src_slot<DIM>(g, x, y, z, i);
-    return Codec<STORE>::ld(fk + a, weight<DIM>(i));
+    return Codec<STORE>::ld(fk + slot_of<DIM>(g, p, tw, x, y, z, i), weight<DIM>(i));
+}
+
+// Buffer gather: for a wave whose nodes all stream in from in-box neighbours
+// (no bounce-back, no periodic wrap) population i sits at plane_i + p - off_i,
+// so the lane offset p is shared by all directions and the plane term is
+// wave-uniform.
+template <int DIM, int STORE>
+__device__ __forceinline__ void bgather(__amdgpu_buffer_rsrc_t rs, const Geometry &g, uint32_t p, uint32_t tw,
+                                        int x, int y, int z, bool wave_fast, float (&f)[Lat<DIM>::Q])
+{
+    constexpr uint32_t SZ = Buf<STORE>::SZ;
+    if (wave_fast) {
+        const uint32_t vo = p * SZ;
+        static_for<Lat<DIM>::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            f[i] = Buf<STORE>::ld(rs, vo, (int)(((int64_t)i * g.Ppad - dir_off<DIM>(g, i)) * SZ), weight<DIM>(i));
+        });
+    } else {
+        static_for<Lat<DIM>::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const uint32_t a = (uint32_t)slot_of<DIM>(g, (int64_t)p, tw, x, y, z, i);
+            f[i] = Buf<STORE>::ld(rs, a * SZ, 0, weight<DIM>(i));
+        });
+    }
 }
 
 __device__ __forceinline__ void coords_of(const Geometry &g, int64_t b, int &x, int &y, int &z)
@@ -160,191 +217,271 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
 enum { MODE_STEP = 0, MODE_MOMENTS = 1 };
 
 // ---------------------------------------------------------------------------
-// k_main: the fused per-node update over a TX x TY x TZ tile.
+// k_main: the fused per-node update as a sweep along the last lattice axis
+// (y in 2-D, z in 3-D).  A block owns a lateral tile (TX in 2-D, TX x TY in
+// 3-D) and a chunk of ZC planes of the sweep axis; it advances W planes per
+// iteration and keeps psi of the planes it needs (window plus two on each
+// side) in an LDS ring of W + 4 planes, so psi is computed once per plane and
+// only the lateral two-node halo is recomputed by neighbouring blocks.
+// Work items are ordered lateral-x fastest, then lateral-y, then chunk, and
+// each of the eight XCDs takes a contiguous range of them, so the blocks that
+// share halo data share an L2.
 // ---------------------------------------------------------------------------
-template <int DIM, int STORE, int MODE, int TX, int TY, int TZ>
+template <int DIM, int STORE, int MODE, int TX, int TY, int W, int ZC>
 __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__restrict__ src,
                                               typename Codec<STORE>::T *__restrict__ dst,
                                               const uint32_t *__restrict__ type, Geometry g, Physics ph,
-                                              Boundary bd, int tiles_x, int tiles_y,
+                                              Boundary bd, int tiles_x, int tiles_y, int n_items,
                                               double *__restrict__ out_rho, double *__restrict__ out_u,
                                               int *__restrict__ flag)
 {
-    using T = typename Codec<STORE>::T;
     constexpr int Q = Lat<DIM>::Q;
-    constexpr int HX = TX + 4, HY = TY + 4, HZ = DIM == 3 ? TZ + 4 : 1;
-    constexpr int NH = HX * HY * HZ;
-    constexpr int NT = TX * TY * (DIM == 3 ? TZ : 1);
-    __shared__ float2 s_psi[NH];
-    __shared__ uint8_t s_sol[NH];
+    constexpr int LY = DIM == 3 ? TY : 1;          // lateral y extent of the tile
+    constexpr int HX = TX + 4, HY = DIM == 3 ? TY + 4 : 1;
+    constexpr int PLANE = HX * HY;                 // lateral halo positions per plane
+    constexpr int R = W + 4;                       // ring planes
+    constexpr int NPT = DIM == 3 ? W : 1;          // nodes per thread per iteration
+    constexpr int NOFF = DIM == 3 ? 125 : 25;      // offsets of the 5^DIM stencil box
+    static_assert(DIM == 3 ? TX * LY == 256 : TX * W == 256, "256 threads per block");
+    static_assert((R & (R - 1)) == 0, "ring size must be a power of two");
+    __shared__ float2 s_psi[R * PLANE];
+    __shared__ uint8_t s_sol[R * PLANE];
     __shared__ double s_red[8];
 
-    const int tile = blockIdx.x;
-    const int tx = tile % tiles_x;
-    const int ty = (tile / tiles_x) % tiles_y;
-    const int tz = tile / (tiles_x * tiles_y);
-    const int x0 = tx * TX, y0 = ty * TY, z0 = DIM == 3 ? tz * TZ : 0;
-    const T *src1 = src + (int64_t)Q * g.Ppad;
-
-    // ---- stage 1: psi_k = rho_k over the tile and its halo (0 on solids)
-    for (int h = threadIdx.x; h < NH; h += 256) {
-        const int lx = h % HX, ly = (h / HX) % HY, lz = h / (HX * HY);
-        int gx = x0 - 2 + lx, gy = y0 - 2 + ly, gz = DIM == 3 ? z0 - 2 + lz : 0;
-        float p1 = 0.0f, p2 = 0.0f;
-        uint8_t sol = 1;
-        const bool need = gx < g.n[0] + 2 && gy < g.n[1] + 2 && (DIM == 2 || gz < g.n[2] + 2);
-        if (need) {
-            gx = map_axis(gx, g.n[0], g.periodic[0]);
-            gy = map_axis(gy, g.n[1], g.periodic[1]);
-            if (DIM == 3) gz = map_axis(gz, g.n[2], g.periodic[2]);
-            const int64_t b = (int64_t)gx + (int64_t)g.n[0] * ((int64_t)gy + (int64_t)g.n[1] * gz);
-            const uint32_t tw = type[b];
-            if (!(tw & T_SOLID)) {
-                const int64_t p = pidx(g, gx, gy, DIM == 3 ? gz : -1);
-                float f[Q];
-                gather<DIM, STORE>(src, g, p, tw, gx, gy, gz, f);
-                float r = 0.0f;
-#pragma unroll
-                for (int i = 0; i < Q; i++) r += f[i];
-                p1 = r;
-                gather<DIM, STORE>(src1, g, p, tw, gx, gy, gz, f);
-                r = 0.0f;
-#pragma unroll
-                for (int i = 0; i < Q; i++) r += f[i];
-                p2 = r;
-                sol = 0;
-            }
-        }
-        s_psi[h] = make_float2(p1, p2);
-        s_sol[h] = sol;
-    }
-    __syncthreads();
-
+    // XCD-aware work item: blocks are dealt round-robin to the 8 XCDs
+    const int per = (int)(gridDim.x + 7) / 8;
+    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     double q_in = 0.0, q_out = 0.0;
-    for (int q = threadIdx.x; q < NT; q += 256) {
-        const int lx = q % TX, ly = (q / TX) % TY, lz = DIM == 3 ? q / (TX * TY) : 0;
-        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (x >= g.n[0] || y >= g.n[1] || (DIM == 3 && z >= g.n[2])) continue;
-        const int64_t b = (int64_t)x + (int64_t)g.n[0] * ((int64_t)y + (int64_t)g.n[1] * z);
-        const uint32_t tw = type[b];
-        if (tw & T_SOLID) {
-            if (MODE == MODE_MOMENTS) {
-                out_rho[b] = 0.0;
-                out_rho[g.N + b] = 0.0;
-                for (int d = 0; d < 3; d++) out_u[d * g.N + b] = 0.0;
-            }
-            continue;
-        }
-        const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
-        const int hc = ((DIM == 3 ? lz + 2 : 0) * HY + ly + 2) * HX + lx + 2;
-        const float2 ps = s_psi[hc];
+    const __amdgpu_buffer_rsrc_t rs0 = comp_rsrc<STORE>(src, 0, Q, g.Ppad);
+    const __amdgpu_buffer_rsrc_t rs1 = comp_rsrc<STORE>(src, 1, Q, g.Ppad);
 
-        // ---- stage 2: forces (eqs. 10-11) and body force
-        float g1[3] = {0.f, 0.f, 0.f}, g2[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
-        const bool near = ph.adhesion && (tw & T_NEARWALL);
-#pragma unroll
-        for (int dz = (DIM == 3 ? -2 : 0); dz <= (DIM == 3 ? 2 : 0); dz++)
-#pragma unroll
-            for (int dy = -2; dy <= 2; dy++)
-#pragma unroll
-                for (int dx = -2; dx <= 2; dx++) {
-                    const int r2 = dx * dx + dy * dy + dz * dz;
-                    const float w = stencil_w<DIM>(r2);
-                    if (r2 == 0 || w == 0.0f) continue;
-                    const int ho = (dz * HY + dy) * HX + dx;
-                    const float2 v = s_psi[hc + ho];
-                    if (dx) { g1[0] = fmaf(w * dx, v.x, g1[0]); g2[0] = fmaf(w * dx, v.y, g2[0]); }
-                    if (dy) { g1[1] = fmaf(w * dy, v.x, g1[1]); g2[1] = fmaf(w * dy, v.y, g2[1]); }
-                    if (dz) { g1[2] = fmaf(w * dz, v.x, g1[2]); g2[2] = fmaf(w * dz, v.y, g2[2]); }
+    if (item < n_items) {
+        const int ns = g.n[DIM - 1];
+        const int tx = item % tiles_x;
+        const int ty = (item / tiles_x) % tiles_y;
+        const int ch = item / (tiles_x * tiles_y);
+        const int x0 = tx * TX, y0 = DIM == 3 ? ty * TY : 0;
+        const int s0 = ch * ZC, s1 = min(s0 + ZC, ns);
+
+        // psi of sweep planes [pa, pb) into the ring
+        auto load_planes = [&](int pa, int pb) {
+            const int cnt = (pb - pa) * PLANE;
+            for (int h = threadIdx.x; h < cnt; h += 256) {
+                const int pl = pa + h / PLANE, r = h % PLANE;
+                const int lx = r % HX, ly = r / HX;
+                int gx = x0 - 2 + lx, gy, gz;
+                if (DIM == 3) { gy = y0 - 2 + ly; gz = pl; }
+                else { gy = pl; gz = 0; }
+                const bool need = gx < g.n[0] + 2 && gy < g.n[1] + 2 && (DIM == 2 || gz < g.n[2] + 2);
+                uint32_t tw = T_SOLID;
+                uint32_t pp = 0;
+                if (need) {
+                    gx = map_axis(gx, g.n[0], g.periodic[0]);
+                    gy = map_axis(gy, g.n[1], g.periodic[1]);
+                    if (DIM == 3) gz = map_axis(gz, g.n[2], g.periodic[2]);
+                    const int64_t b = (int64_t)gx + (int64_t)g.n[0] * ((int64_t)gy + (int64_t)g.n[1] * gz);
+                    tw = type[b];
+                    pp = (uint32_t)pidx(g, gx, gy, DIM == 3 ? gz : -1);
                 }
-        if (near) {
-#pragma unroll
-            for (int dz = (DIM == 3 ? -2 : 0); dz <= (DIM == 3 ? 2 : 0); dz++)
-#pragma unroll
-                for (int dy = -2; dy <= 2; dy++)
-#pragma unroll
-                    for (int dx = -2; dx <= 2; dx++) {
-                        const int r2 = dx * dx + dy * dy + dz * dz;
-                        const float w = stencil_w<DIM>(r2);
-                        if (r2 == 0 || w == 0.0f) continue;
-                        const int ho = (dz * HY + dy) * HX + dx;
-                        const float sv = (float)s_sol[hc + ho];
-                        if (dx) A[0] = fmaf(w * dx, sv, A[0]);
-                        if (dy) A[1] = fmaf(w * dy, sv, A[1]);
-                        if (dz) A[2] = fmaf(w * dz, sv, A[2]);
+                const bool fluid = !(tw & T_SOLID);
+                const bool wave_fast = __ballot(fluid && (tw & (T_BBMASK | T_EDGE))) == 0;
+                float p1 = 0.0f, p2 = 0.0f;
+                if (fluid) {
+                    float f[Q];
+                    bgather<DIM, STORE>(rs0, g, pp, tw, gx, gy, gz, wave_fast, f);
+                    static_for<Q>([&](auto ic) { p1 += f[decltype(ic)::value]; });
+                    bgather<DIM, STORE>(rs1, g, pp, tw, gx, gy, gz, wave_fast, f);
+                    static_for<Q>([&](auto ic) { p2 += f[decltype(ic)::value]; });
+                }
+                const int slot = ((pl + 4 * R) & (R - 1)) * PLANE + r;
+                s_psi[slot] = make_float2(p1, p2);
+                s_sol[slot] = fluid ? 0 : 1;
+            }
+        };
+
+        load_planes(s0 - 2, s0 + 2);
+        for (int w0 = s0; w0 < s1; w0 += W) {
+            __syncthreads();                      // ring slots of w0-6..w0-3 are free
+            load_planes(w0 + 2, w0 + W + 2);
+            __syncthreads();
+#pragma unroll 1
+            for (int k = 0; k < NPT; k++) {
+                int lx, ly, sv;
+                if (DIM == 3) { lx = threadIdx.x % TX; ly = threadIdx.x / TX; sv = w0 + k; }
+                else { lx = threadIdx.x % TX; ly = 0; sv = w0 + threadIdx.x / TX; }
+                const int x = x0 + lx;
+                const int y = DIM == 3 ? y0 + ly : sv;
+                const int z = DIM == 3 ? sv : 0;
+                const bool valid = x < g.n[0] && sv < s1 && (DIM == 2 || y < g.n[1]);
+                const int64_t b = valid ? (int64_t)x + (int64_t)g.n[0] * ((int64_t)y + (int64_t)g.n[1] * z) : 0;
+                const uint32_t tw = valid ? type[b] : T_SOLID;
+                const bool fluid = !(tw & T_SOLID);
+                const bool wave_fast = __ballot(fluid && (tw & (T_BBMASK | T_EDGE))) == 0;
+                if (!fluid) {
+                    if (MODE == MODE_MOMENTS && valid) {
+                        out_rho[b] = 0.0;
+                        out_rho[g.N + b] = 0.0;
+                        out_u[b] = 0.0;
+                        out_u[g.N + b] = 0.0;
+                        out_u[2 * g.N + b] = 0.0;
                     }
-        }
-        const float r1 = ps.x, r2 = ps.y, rt = r1 + r2;
-        float F1[3], F2[3];
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            F1[d] = -ph.G12 * r1 * g2[d] - ph.Gw[0] * r1 * A[d] + (r1 / rt) * ph.Fb[d];
-            F2[d] = -ph.G12 * r2 * g1[d] - ph.Gw[1] * r2 * A[d] + (r2 / rt) * ph.Fb[d];
-        }
+                    continue;
+                }
+                const uint32_t p = (uint32_t)pidx(g, x, y, DIM == 3 ? z : -1);
+                // base[d]: ring index of the lateral corner (-2, -2) of the
+                // node's neighbourhood in sweep plane sv + d - 2, so every
+                // stencil offset below is a non-negative immediate
+                const int corner = (DIM == 3 ? ly * HX : 0) + lx;
+                int base[5];
+                static_for<5>([&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    base[d] = ((sv + d - 2 + 4 * R) & (R - 1)) * PLANE + corner;
+                });
+                constexpr int CEN = (DIM == 3 ? 2 * HX : 0) + 2;   // the node itself
+                const float2 ps = s_psi[base[2] + CEN];
 
-        // ---- stage 3: common velocity (eqs. 7-8)
-        float fa[Q], fb[Q];
-        gather<DIM, STORE>(src, g, p, tw, x, y, z, fa);
-        gather<DIM, STORE>(src1, g, p, tw, x, y, z, fb);
-        float J1[3] = {0.f, 0.f, 0.f}, J2[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-#pragma unroll
-            for (int d = 0; d < DIM; d++) {
-                const int e = Lat<DIM>::E[i][d];
-                if (e == 1) { J1[d] += fa[i]; J2[d] += fb[i]; }
-                else if (e == -1) { J1[d] -= fa[i]; J2[d] -= fb[i]; }
+                // ---- wall adhesion (eq. 11): only nodes with a solid within the stencil
+                float A[3] = {0.f, 0.f, 0.f};
+                if (ph.adhesion && (tw & T_NEARWALL)) {
+                    static_for<NOFF>([&](auto oc) {
+                        constexpr int o = decltype(oc)::value;
+                        constexpr int dx = o % 5 - 2, dy = (o / 5) % 5 - 2, dz = DIM == 3 ? o / 25 - 2 : 0;
+                        constexpr int r2 = dx * dx + dy * dy + dz * dz;
+                        constexpr float w = stencil_w<DIM>(r2);
+                        if constexpr (r2 != 0 && w != 0.0f) {
+                            constexpr int ddy = DIM == 3 ? dy : 0, ddz = DIM == 3 ? dz : dy;
+                            const float sv1 = (float)s_sol[base[2 + ddz] + CEN + ddy * HX + dx];
+                            if constexpr (dx != 0) A[0] = fmaf(w * dx, sv1, A[0]);
+                            if constexpr (dy != 0) A[1] = fmaf(w * dy, sv1, A[1]);
+                            if constexpr (dz != 0) A[2] = fmaf(w * dz, sv1, A[2]);
+                        }
+                    });
+                }
+                // ---- forces (eqs. 10-11): the stencil in pairs of opposite
+                // offsets, one sweep-plane distance at a time (the loop bounds
+                // how many LDS reads are in flight)
+                float g1[3] = {0.f, 0.f, 0.f}, g2[3] = {0.f, 0.f, 0.f};
+#pragma unroll 1
+                for (int sd = 0; sd <= 2; sd++) {
+                    const int bp = ((sv + sd + 4 * R) & (R - 1)) * PLANE + corner + CEN;
+                    const int bm = ((sv - sd + 4 * R) & (R - 1)) * PLANE + corner + CEN;
+                    auto plane = [&](auto sdc) {
+                        constexpr int SD = decltype(sdc)::value;
+                        static_for<25>([&](auto oc) {
+                            constexpr int o = decltype(oc)::value;
+                            constexpr int a = o % 5 - 2, bq = o / 5 - 2;   // lateral offsets
+                            // (dx, dy, dz) of the offset and its lateral / sweep split
+                            constexpr int dx = a, dy = DIM == 3 ? bq : SD, dz = DIM == 3 ? SD : 0;
+                            constexpr int lat_y = DIM == 3 ? bq : 0;
+                            constexpr int r2 = dx * dx + dy * dy + dz * dz;
+                            constexpr float w = stencil_w<DIM>(r2);
+                            // the half of the stencil with a positive first nonzero of (sweep, lateral-y, x)
+                            constexpr bool half = SD > 0 || (lat_y > 0 || (lat_y == 0 && dx > 0));
+                            constexpr bool in2d = DIM == 3 || bq == 0;
+                            if constexpr (half && in2d && w != 0.0f) {
+                                constexpr int ho = lat_y * HX + dx;
+                                const float2 vp = s_psi[bp + ho];
+                                const float2 vm = s_psi[bm - ho];
+                                const float d1 = vp.x - vm.x, d2 = vp.y - vm.y;
+                                if constexpr (dx != 0) { g1[0] = fmaf(w * dx, d1, g1[0]); g2[0] = fmaf(w * dx, d2, g2[0]); }
+                                if constexpr (dy != 0) { g1[1] = fmaf(w * dy, d1, g1[1]); g2[1] = fmaf(w * dy, d2, g2[1]); }
+                                if constexpr (dz != 0) { g1[2] = fmaf(w * dz, d1, g1[2]); g2[2] = fmaf(w * dz, d2, g2[2]); }
+                            }
+                        });
+                    };
+                    if (sd == 0) plane(std::integral_constant<int, 0>{});
+                    else if (sd == 1) plane(std::integral_constant<int, 1>{});
+                    else plane(std::integral_constant<int, 2>{});
+                }
+                const float r1 = ps.x, r2 = ps.y, rt = r1 + r2;
+                const float w1 = r1 / rt, w2 = r2 / rt;
+                float F1[3], F2[3];
+                static_for<3>([&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    F1[d] = -ph.G12 * r1 * g2[d] - ph.Gw[0] * r1 * A[d] + w1 * ph.Fb[d];
+                    F2[d] = -ph.G12 * r2 * g1[d] - ph.Gw[1] * r2 * A[d] + w2 * ph.Fb[d];
+                });
+
+                // ---- common velocity (eqs. 7-8).  Component 2 is gathered
+                // twice (the second time from L1/L2 after component 1 is
+                // stored) so that only one component is held in registers.
+                PairF<DIM> qa;
+                float J1[3], J2[3];
+                {
+                    float f[Q];
+                    bgather<DIM, STORE>(rs0, g, p, tw, x, y, z, wave_fast, f);
+                    to_pairs<DIM>(f, qa);
+                    pair_momentum<DIM>(qa, J1);
+                    bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f);
+                    PairF<DIM> qt;
+                    to_pairs<DIM>(f, qt);
+                    pair_momentum<DIM>(qt, J2);
+                }
+                float u[3];
+                const float irt = 1.0f / rt;
+                static_for<3>([&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    u[d] = (J1[d] + J2[d] + 0.5f * (F1[d] + F2[d])) * irt;
+                });
+
+                if (MODE == MODE_MOMENTS) {
+                    out_rho[b] = r1;
+                    out_rho[g.N + b] = r2;
+                    out_u[b] = u[0];
+                    out_u[g.N + b] = u[1];
+                    out_u[2 * g.N + b] = u[2];
+                    continue;
+                }
+                if (!(rt > 0.0f) || !isfinite(rt) || !isfinite(u[0] + u[1] + u[2])) *flag = 1;
+
+                if (tw & T_ROLE) {
+                    const int slot = bd.bslot[b];
+                    float *fF = bd.faceF + (int64_t)slot * 6;
+                    fF[0] = F1[0]; fF[1] = F1[1]; fF[2] = F1[2];
+                    fF[3] = F2[0]; fF[4] = F2[1]; fF[5] = F2[2];
+                    if (tw & T_XPRIME) {
+                        const float un = bd.out_sign * pick3(u, bd.out_axis);
+                        bd.faceU[slot] = un;
+                        q_out += (double)rt * (double)un;
+                    }
+                    if (tw & T_INLET) {
+                        const Patch pt = bd.patch[(tw & T_PATCH_MASK) >> T_PATCH_SHIFT];
+                        q_in += (double)rt * (double)(pt.sign * pick3(u, pt.axis));
+                    }
+                    if ((tw & T_OUTLET) && bd.chi_on) continue;   // collided by k_outlet
+                }
+
+                // ---- MRT collision of each component, stored at x
+                const __amdgpu_buffer_rsrc_t rd0 = comp_rsrc<STORE>(dst, 0, Q, g.Ppad);
+                const __amdgpu_buffer_rsrc_t rd1 = comp_rsrc<STORE>(dst, 1, Q, g.Ppad);
+                const uint32_t vo = p * Buf<STORE>::SZ;
+                float fo[Q];
+                const Rates ra = {ph.se[0], ph.seps[0], ph.sq, ph.snu[0]};
+                collide_pairs<DIM>(qa, r1, J1, u, F1, ra, fo);
+                static_for<Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    Buf<STORE>::st(rd0, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i));
+                });
+                PairF<DIM> qb;
+                {
+                    float f[Q];
+                    bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f);
+                    to_pairs<DIM>(f, qb);
+                }
+                const Rates rb = {ph.se[1], ph.seps[1], ph.sq, ph.snu[1]};
+                collide_pairs<DIM>(qb, r2, J2, u, F2, rb, fo);
+                static_for<Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    Buf<STORE>::st(rd1, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i));
+                });
             }
-        }
-        float u[3];
-        const float irt = 1.0f / rt;
-#pragma unroll
-        for (int d = 0; d < 3; d++) u[d] = (J1[d] + J2[d] + 0.5f * (F1[d] + F2[d])) * irt;
-
-        if (MODE == MODE_MOMENTS) {
-            out_rho[b] = r1;
-            out_rho[g.N + b] = r2;
-            for (int d = 0; d < 3; d++) out_u[d * g.N + b] = u[d];
-            continue;
-        }
-        if (!(rt > 0.0f) || !isfinite(rt) || !isfinite(u[0] + u[1] + u[2])) *flag = 1;
-
-        if (tw & T_ROLE) {
-            const int slot = bd.bslot[b];
-            float *fF = bd.faceF + (int64_t)slot * 6;
-#pragma unroll
-            for (int d = 0; d < 3; d++) { fF[d] = F1[d]; fF[3 + d] = F2[d]; }
-            if (tw & T_XPRIME) {
-                const float un = bd.out_sign * u[bd.out_axis];
-                bd.faceU[slot] = un;
-                q_out += (double)rt * (double)un;
-            }
-            if (tw & T_INLET) {
-                const Patch &pt = bd.patch[(tw & T_PATCH_MASK) >> T_PATCH_SHIFT];
-                q_in += (double)rt * (double)(pt.sign * u[pt.axis]);
-            }
-            if ((tw & T_OUTLET) && bd.chi_on) continue;   // collided by k_outlet
-        }
-
-        // ---- stage 5: MRT collision of each component, stored at x
-        {
-            const Rates s1 = {ph.se[0], ph.seps[0], ph.sq, ph.snu[0]};
-            collide<DIM>(fa, r1, J1, u, F1, s1);
-            T *d1 = dst;
-#pragma unroll
-            for (int i = 0; i < Q; i++) Codec<STORE>::st(d1 + (int64_t)i * g.Ppad + p, fa[i], weight<DIM>(i));
-            const Rates s2 = {ph.se[1], ph.seps[1], ph.sq, ph.snu[1]};
-            collide<DIM>(fb, r2, J2, u, F2, s2);
-            T *d2 = dst + (int64_t)Q * g.Ppad;
-#pragma unroll
-            for (int i = 0; i < Q; i++) Codec<STORE>::st(d2 + (int64_t)i * g.Ppad + p, fb[i], weight<DIM>(i));
         }
     }
     if (MODE == MODE_STEP && bd.qpart) {
         block_sum2(q_in, q_out, s_red);
-        if (threadIdx.x == 0) {
-            bd.qpart[2 * blockIdx.x] = q_in;
-            bd.qpart[2 * blockIdx.x + 1] = q_out;
+        if (threadIdx.x == 0 && item < n_items) {
+            bd.qpart[2 * item] = q_in;
+            bd.qpart[2 * item + 1] = q_out;
         }
     }
 }
@@ -354,6 +491,24 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
 __device__ __forceinline__ double chi_of(double qin, double qout)
 {
     return (fabs(qout) < 1e-30 || qin * qout <= 0.0) ? 1.0 : qin / qout;
+}
+
+// Density and momentum of the populations of one component.
+template <int DIM>
+__device__ __forceinline__ void moments_of(const float (&f)[Lat<DIM>::Q], float &rho, float (&J)[3])
+{
+    rho = 0.0f;
+    J[0] = J[1] = J[2] = 0.0f;
+    static_for<Lat<DIM>::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        rho += f[i];
+        static_for<3>([&](auto dc) {
+            constexpr int d = decltype(dc)::value;
+            constexpr int e = Lat<DIM>::E[i][d];
+            if constexpr (e == 1) J[d] += f[i];
+            else if constexpr (e == -1) J[d] -= f[i];
+        });
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -387,39 +542,41 @@ __global__ __launch_bounds__(256) void k_outlet(const typename Codec<STORE>::T *
     float fa[Q], fb[Q];
     gather<DIM, STORE>(src, g, p, tw, x, y, z, fa);
     gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw, x, y, z, fb);
-    float r1 = 0.f, r2 = 0.f, J1[3] = {0.f, 0.f, 0.f}, J2[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        r1 += fa[i];
-        r2 += fb[i];
-#pragma unroll
-        for (int d = 0; d < DIM; d++) {
-            const int e = Lat<DIM>::E[i][d];
-            if (e == 1) { J1[d] += fa[i]; J2[d] += fb[i]; }
-            else if (e == -1) { J1[d] -= fa[i]; J2[d] -= fb[i]; }
-        }
-    }
+    float r1, r2, J1[3], J2[3];
+    moments_of<DIM>(fa, r1, J1);
+    moments_of<DIM>(fb, r2, J2);
     const float *fF = bd.faceF + (int64_t)rec.slotN * 6;
-    float F1[3], F2[3], u[3];
+    float F1[3] = {fF[0], fF[1], fF[2]}, F2[3] = {fF[3], fF[4], fF[5]}, u[3];
     const float rt = r1 + r2;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        F1[d] = fF[d];
-        F2[d] = fF[3 + d];
+    static_for<3>([&](auto dc) {
+        constexpr int d = decltype(dc)::value;
         u[d] = (J1[d] + J2[d] + 0.5f * (F1[d] + F2[d])) / rt;
+    });
+    if (rec.slotP >= 0) {
+        // eq. (22): the outward velocity is chi times that of x_{N-1}
+        const float un = (float)(chi * (double)bd.faceU[rec.slotP]) * bd.out_sign;
+        if (bd.out_axis == 0) u[0] = un;
+        else if (bd.out_axis == 1) u[1] = un;
+        else u[2] = un;
     }
-    if (rec.slotP >= 0) u[bd.out_axis] = (float)(chi * (double)(bd.out_sign * bd.faceU[rec.slotP])) * bd.out_sign;
     if (!(rt > 0.0f) || !isfinite(rt) || !isfinite(u[0] + u[1] + u[2])) *flag = 1;
+    float fo[Q];
+    PairF<DIM> q;
+    to_pairs<DIM>(fa, q);
     const Rates s1 = {ph.se[0], ph.seps[0], ph.sq, ph.snu[0]};
-    collide<DIM>(fa, r1, J1, u, F1, s1);
+    collide_pairs<DIM>(q, r1, J1, u, F1, s1, fo);
+    static_for<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        Codec<STORE>::st(dst + (int64_t)i * g.Ppad + p, fo[i], weight<DIM>(i));
+    });
+    to_pairs<DIM>(fb, q);
     const Rates s2 = {ph.se[1], ph.seps[1], ph.sq, ph.snu[1]};
-    collide<DIM>(fb, r2, J2, u, F2, s2);
+    collide_pairs<DIM>(q, r2, J2, u, F2, s2, fo);
     T *d2 = dst + (int64_t)Q * g.Ppad;
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        Codec<STORE>::st(dst + (int64_t)i * g.Ppad + p, fa[i], weight<DIM>(i));
-        Codec<STORE>::st(d2 + (int64_t)i * g.Ppad + p, fb[i], weight<DIM>(i));
-    }
+    static_for<Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        Codec<STORE>::st(d2 + (int64_t)i * g.Ppad + p, fo[i], weight<DIM>(i));
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -446,72 +603,82 @@ __global__ __launch_bounds__(256) void k_inlet(typename Codec<STORE>::T *__restr
         const int64_t p1 = pidx(g, x1, y1, DIM == 3 ? z1 : -1);
         const int64_t p2 = pidx(g, x2, y2, DIM == 3 ? z2 : -1);
         const bool x2_fluid = !(tw2 & T_SOLID);
-        float up[3] = {0.f, 0.f, 0.f};
-        up[pt.axis] = pt.sign * pt.u_n;
+        const float un = pt.sign * pt.u_n;
+        const float up[3] = {pt.axis == 0 ? un : 0.0f, pt.axis == 1 ? un : 0.0f, pt.axis == 2 ? un : 0.0f};
         // rho_k(x2), u(x2) from the streamed f at t+1 with this step's force
-        float f2[2][Q], r2[2] = {0.f, 0.f}, u2[3] = {0.f, 0.f, 0.f};
+        float fa2[Q], fb2[Q], ra2 = 0.f, rb2 = 0.f, u2[3] = {0.f, 0.f, 0.f};
         if (x2_fluid) {
-            float J[3] = {0.f, 0.f, 0.f};
+            float Ja[3], Jb[3];
+            gather<DIM, STORE>(dst, g, p2, tw2, x2, y2, z2, fa2);
+            gather<DIM, STORE>(dst + (int64_t)Q * g.Ppad, g, p2, tw2, x2, y2, z2, fb2);
+            moments_of<DIM>(fa2, ra2, Ja);
+            moments_of<DIM>(fb2, rb2, Jb);
             const float *F2 = bd.faceF + (int64_t)rec.slot2 * 6;
-#pragma unroll
-            for (int k = 0; k < 2; k++) {
-                gather<DIM, STORE>(dst + (int64_t)k * Q * g.Ppad, g, p2, tw2, x2, y2, z2, f2[k]);
-#pragma unroll
-                for (int i = 0; i < Q; i++) {
-                    r2[k] += f2[k][i];
-#pragma unroll
-                    for (int d = 0; d < DIM; d++) J[d] += Lat<DIM>::E[i][d] * f2[k][i];
-                }
-            }
-            const float rt = r2[0] + r2[1];
-#pragma unroll
-            for (int d = 0; d < 3; d++) u2[d] = (J[d] + 0.5f * (F2[d] + F2[3 + d])) / rt;
+            const float rt = ra2 + rb2;
+            static_for<3>([&](auto dc) {
+                constexpr int d = decltype(dc)::value;
+                u2[d] = (Ja[d] + Jb[d] + 0.5f * (F2[d] + F2[3 + d])) / rt;
+            });
+        } else {
+            static_for<Q>([&](auto ic) { fa2[decltype(ic)::value] = 0.0f; fb2[decltype(ic)::value] = 0.0f; });
         }
         const float *F1 = bd.faceF + (int64_t)rec.slot1 * 6;
-        for (int k = 0; k < 2; k++) {
+        static_for<2>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
             T *dk = dst + (int64_t)k * Q * g.Ppad;
+            const float rho_p = pt.rho[k];
+            const float rho2 = k == 0 ? ra2 : rb2;
+            const float(&f2)[Q] = k == 0 ? fa2 : fb2;
             float f1[Q];
             gather<DIM, STORE>(dk, g, p1, tw1, x1, y1, z1, f1);
             // eq. (13)/(14) on the populations entering the domain
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                if (Lat<DIM>::E[i][pt.axis] * pt.sign <= 0) continue;
-                const float neq = x2_fluid ? f2[k][i] - feq<DIM>(i, r2[k], u2) : 0.0f;
-                f1[i] = feq<DIM>(i, pt.rho[k], up) + neq;
-            }
+            static_for<Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if (e_axis<DIM>(i, pt.axis) * pt.sign > 0) {
+                    const float neq = x2_fluid ? f2[i] - feq<DIM>(i, rho2, u2) : 0.0f;
+                    f1[i] = feq<DIM>(i, rho_p, up) + neq;
+                }
+            });
             if (pt.alpha_on) {
                 // eqs. (15)-(19): alpha_i = w_i sum_d e_id dJ_d / D_d over the
                 // entering set, dJ = rho_k^p u^p - (sum_i e_i f_i + F^k/2)
-                float J[3] = {0.f, 0.f, 0.f}, D[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                for (int i = 0; i < Q; i++) {
-#pragma unroll
-                    for (int d = 0; d < DIM; d++) J[d] += Lat<DIM>::E[i][d] * f1[i];
-                    if (Lat<DIM>::E[i][pt.axis] * pt.sign > 0) {
-#pragma unroll
-                        for (int d = 0; d < DIM; d++)
-                            D[d] += weight<DIM>(i) * (float)(Lat<DIM>::E[i][d] * Lat<DIM>::E[i][d]);
+                float rr, J[3], D[3] = {0.f, 0.f, 0.f};
+                moments_of<DIM>(f1, rr, J);
+                static_for<Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    if (e_axis<DIM>(i, pt.axis) * pt.sign > 0) {
+                        static_for<3>([&](auto dc) {
+                            constexpr int d = decltype(dc)::value;
+                            constexpr int e = Lat<DIM>::E[i][d];
+                            if constexpr (e != 0) D[d] += weight<DIM>(i);
+                        });
                     }
-                }
+                });
                 float dJ[3];
-#pragma unroll
-                for (int d = 0; d < 3; d++) dJ[d] = pt.rho[k] * up[d] - (J[d] + 0.5f * F1[3 * k + d]);
-#pragma unroll
-                for (int i = 0; i < Q; i++) {
-                    if (Lat<DIM>::E[i][pt.axis] * pt.sign <= 0) continue;
-                    float a = 0.0f;
-#pragma unroll
-                    for (int d = 0; d < DIM; d++)
-                        if (Lat<DIM>::E[i][d] != 0) a += weight<DIM>(i) * Lat<DIM>::E[i][d] * dJ[d] / D[d];
-                    f1[i] += a;
-                }
+                static_for<3>([&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    dJ[d] = rho_p * up[d] - (J[d] + 0.5f * F1[3 * k + d]);
+                });
+                static_for<Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    if (e_axis<DIM>(i, pt.axis) * pt.sign > 0) {
+                        float a = 0.0f;
+                        static_for<3>([&](auto dc) {
+                            constexpr int d = decltype(dc)::value;
+                            constexpr int e = Lat<DIM>::E[i][d];
+                            if constexpr (e != 0) a += weight<DIM>(i) * (float)e * dJ[d] / D[d];
+                        });
+                        f1[i] += a;
+                    }
+                });
             }
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                if (Lat<DIM>::E[i][pt.axis] * pt.sign <= 0) continue;
-                Codec<STORE>::st(dk + (int64_t)i * g.Ppad + src_slot<DIM>(g, x1, y1, z1, i), f1[i], weight<DIM>(i));
-            }
-        }
+            static_for<Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if (e_axis<DIM>(i, pt.axis) * pt.sign > 0)
+                    Codec<STORE>::st(dk + (int64_t)i * g.Ppad + src_slot<DIM>(g, x1, y1, z1, i), f1[i],
+                                     weight<DIM>(i));
+            });
+        });
         return;
     }
     // eq. (21): partial sums of the outward normal velocity over x_{N-1}
@@ -525,17 +692,17 @@ __global__ __launch_bounds__(256) void k_inlet(typename Codec<STORE>::T *__restr
             const uint32_t tw = type[rec.bP];
             const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
             float rt = 0.f, J = 0.f;
-            for (int k = 0; k < 2; k++) {
-                float f[Q];
+            static_for<2>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                float f[Q], rk, Jk[3];
                 gather<DIM, STORE>(dst + (int64_t)k * Q * g.Ppad, g, p, tw, x, y, z, f);
-#pragma unroll
-                for (int i = 0; i < Q; i++) {
-                    rt += f[i];
-                    J += (float)(Lat<DIM>::E[i][bd.out_axis] * bd.out_sign) * f[i];
-                }
-            }
+                moments_of<DIM>(f, rk, Jk);
+                rt += rk;
+                J += bd.out_sign * pick3(Jk, bd.out_axis);
+            });
             const float *F = bd.faceF + (int64_t)rec.slotP * 6;
-            J += 0.5f * bd.out_sign * (F[bd.out_axis] + F[3 + bd.out_axis]);
+            const float Fa[3] = {F[0], F[1], F[2]}, Fb[3] = {F[3], F[4], F[5]};
+            J += 0.5f * bd.out_sign * (pick3(Fa, bd.out_axis) + pick3(Fb, bd.out_axis));
             su = (double)(J / rt);
             cnt = 1.0;
         }
@@ -581,22 +748,24 @@ __global__ __launch_bounds__(256) void k_outlet_fill(const typename Codec<STORE>
         pp = pidx(g, xp, yp, DIM == 3 ? zp : -1);
     }
     const float uc = (float)Uc;
-    for (int k = 0; k < 2; k++) {
+    static_for<2>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
         const T *sk = src + (int64_t)k * Q * g.Ppad;
         T *dk = dst + (int64_t)k * Q * g.Ppad;
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            if (Lat<DIM>::E[i][bd.out_axis] * bd.out_sign >= 0) continue;
-            const int64_t a = (int64_t)i * g.Ppad + src_slot<DIM>(g, x, y, z, i);
-            const float prev = Codec<STORE>::ld(sk + a, weight<DIM>(i));
-            float v = prev;
-            if (rec.slotP >= 0) {
-                const float fp = gather1<DIM, STORE>(dk, g, pp, twp, xp, yp, zp, i);
-                v = (prev + uc * fp) / (1.0f + uc);
+        static_for<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if (e_axis<DIM>(i, bd.out_axis) * bd.out_sign < 0) {
+                const int64_t a = (int64_t)i * g.Ppad + src_slot<DIM>(g, x, y, z, i);
+                const float prev = Codec<STORE>::ld(sk + a, weight<DIM>(i));
+                float v = prev;
+                if (rec.slotP >= 0) {
+                    const float fp = gather1<DIM, STORE>(dk, g, pp, twp, xp, yp, zp, i);
+                    v = (prev + uc * fp) / (1.0f + uc);
+                }
+                Codec<STORE>::st(dk + a, v, weight<DIM>(i));
             }
-            Codec<STORE>::st(dk + a, v, weight<DIM>(i));
-        }
-    }
+        });
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -616,13 +785,11 @@ __global__ void k_scatter(typename Codec<STORE>::T *__restrict__ dst, const uint
     const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
     for (int k = 0; k < 2; k++) {
         auto *dk = dst + (int64_t)k * Q * g.Ppad;
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const bool bb = (tw >> i) & 1u;
-            const int64_t a = bb ? (int64_t)Lat<DIM>::OPP[i] * g.Ppad + p
-                                 : (int64_t)i * g.Ppad + src_slot<DIM>(g, x, y, z, i);
-            Codec<STORE>::st(dk + a, (float)f[((int64_t)k * Q + i) * g.N + b], weight<DIM>(i));
-        }
+        static_for<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            Codec<STORE>::st(dk + slot_of<DIM>(g, p, tw | T_EDGE, x, y, z, i),
+                             (float)f[((int64_t)k * Q + i) * g.N + b], weight<DIM>(i));
+        });
     }
 }
 
@@ -644,7 +811,10 @@ __global__ void k_gather_state(const typename Codec<STORE>::T *__restrict__ src,
         const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
         float v[Q];
         gather<DIM, STORE>(src + (int64_t)k * Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, v);
-        for (int i = 0; i < Q; i++) f[((int64_t)k * Q + i) * g.N + b] = (double)v[i];
+        static_for<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            f[((int64_t)k * Q + i) * g.N + b] = (double)v[i];
+        });
     }
 }
 
@@ -657,11 +827,17 @@ __global__ void k_feq_state(const double *__restrict__ rho0, const double *__res
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= N) return;
     float u[3] = {0.f, 0.f, 0.f};
-    if (u0)
-        for (int d = 0; d < 3; d++) u[d] = (float)u0[d * N + b];
+    if (u0) {
+        u[0] = (float)u0[b];
+        u[1] = (float)u0[N + b];
+        u[2] = (float)u0[2 * N + b];
+    }
     for (int k = 0; k < 2; k++) {
         const float r = (float)rho0[k * N + b];
-        for (int i = 0; i < Q; i++) f[((int64_t)k * Q + i) * N + b] = (double)feq<DIM>(i, r, u);
+        static_for<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            f[((int64_t)k * Q + i) * N + b] = (double)feq<DIM>(i, r, u);
+        });
     }
 }
 
@@ -681,10 +857,10 @@ __global__ __launch_bounds__(256) void k_mass(const typename Codec<STORE>::T *__
         coords_of(g, b, x, y, z);
         const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
         float f[Q];
-        gather<DIM, STORE>(src, g, p, tw, x, y, z, f);
-        for (int i = 0; i < Q; i++) m1 += (double)f[i];
-        gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw, x, y, z, f);
-        for (int i = 0; i < Q; i++) m2 += (double)f[i];
+        gather<DIM, STORE>(src, g, p, tw | T_EDGE, x, y, z, f);
+        static_for<Q>([&](auto ic) { m1 += (double)f[decltype(ic)::value]; });
+        gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, f);
+        static_for<Q>([&](auto ic) { m2 += (double)f[decltype(ic)::value]; });
     }
     block_sum2(m1, m2, s_red);
     if (threadIdx.x == 0) {

@@ -12,12 +12,30 @@
 // (eq. 6) and forcing moments (eq. 9):
 //     f* = f - T^-1 [ S (m - m_eq) - (I - S/2) F_m ],   m = T f   (eq. 1)
 // where T^-1 = T^T diag(1/|row|^2) because the rows are orthogonal.
+//
+// Every loop over directions, moment rows and stencil offsets is expanded at
+// compile time (static_for), so all matrix entries and weights are literals
+// in the generated code.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace lbm {
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// Calls f(std::integral_constant<int, i>) for i = 0 .. N-1.
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <int DIM> struct Lat;
 
@@ -104,89 +122,176 @@ __host__ __device__ constexpr int tnorm(int r)
     return acc;
 }
 
+// Row parity under e -> -e.
+template <int DIM>
+__host__ __device__ constexpr bool row_odd(int r)
+{
+    for (int i = 1; i < Lat<DIM>::Q; i++)
+        if (trow<DIM>(r, i) != 0) return trow<DIM>(r, Lat<DIM>::OPP[i]) == -trow<DIM>(r, i);
+    return false;
+}
+
+// Opposite pairs: the member listed first in the velocity order.
+template <int DIM> struct Pairs {
+    static constexpr int P = (Lat<DIM>::Q - 1) / 2;
+    static constexpr int first(int p)
+    {
+        int n = 0;
+        for (int i = 1; i < Lat<DIM>::Q; i++)
+            if (i < Lat<DIM>::OPP[i]) {
+                if (n == p) return i;
+                n++;
+            }
+        return 0;
+    }
+};
+
 // Relaxation rates of one component (eq. 4): s_rho = s_j = 1.
 struct Rates {
     float se, seps, sq, snu;
 };
 
-// Post-collision populations of one node and one component, in place.
-//   f    : populations f_i^k (post-streaming)
-//   rho  : rho_k ; J : sum_i e_i f_i^k
-//   u    : common velocity used by feq and the forcing term
-//   F    : total force on component k
+// Populations of one node and component in pair form: s_p = f_i + f_ibar,
+// d_p = f_i - f_ibar.  Even moment rows use only s_p and the rest
+// population, odd rows only d_p, which halves both transforms.
+template <int DIM> struct PairF {
+    float f0;
+    float s[Pairs<DIM>::P];
+    float d[Pairs<DIM>::P];
+};
+
 template <int DIM>
-__device__ __forceinline__ void collide(float (&f)[Lat<DIM>::Q], float rho, const float (&J)[3],
-                                        const float (&u)[3], const float (&F)[3], const Rates &s)
+__device__ __forceinline__ void to_pairs(const float (&f)[Lat<DIM>::Q], PairF<DIM> &q)
 {
-    constexpr int Q = Lat<DIM>::Q;
-    float m[Q];
-#pragma unroll
-    for (int r = 0; r < Q; r++) {
+    q.f0 = f[0];
+    static_for<Pairs<DIM>::P>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = Pairs<DIM>::first(p), o = Lat<DIM>::OPP[i];
+        q.s[p] = f[i] + f[o];
+        q.d[p] = f[i] - f[o];
+    });
+}
+
+template <int DIM>
+__device__ __forceinline__ void pair_momentum(const PairF<DIM> &q, float (&J)[3])
+{
+    static_for<3>([&](auto dc) {
+        constexpr int d = decltype(dc)::value;
         float acc = 0.0f;
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            const int t = trow<DIM>(r, i);
-            if (t == 1) acc += f[i];
-            else if (t == -1) acc -= f[i];
-            else if (t != 0) acc = fmaf((float)t, f[i], acc);
-        }
-        m[r] = acc;
-    }
+        static_for<Pairs<DIM>::P>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int e = Lat<DIM>::E[Pairs<DIM>::first(p)][d];
+            if constexpr (e == 1) acc += q.d[p];
+            else if constexpr (e == -1) acc -= q.d[p];
+        });
+        J[d] = acc;
+    });
+}
+
+// Relaxed non-equilibrium part of moment row R divided by |row R|^2:
+//   a_R = [ s_R (m_R - m_eq,R) - (1 - s_R/2) F_m,R ] / |T_R|^2
+// with the closed-form equilibrium moments of eq. (6) and forcing moments of
+// eq. (9).  Momentum rows (s_j = 1) use J - rho u - F/2 directly.
+template <int DIM, int R>
+__device__ __forceinline__ float relax_row(float m, float rho, const float (&J)[3], const float (&u)[3],
+                                           const float (&F)[3], const Rates &s, float uu, float uF)
+{
     const float ux = u[0], uy = u[1], uz = u[2];
     const float Fx = F[0], Fy = F[1], Fz = F[2];
-    const float uu = ux * ux + uy * uy + uz * uz;
-    const float uF = ux * Fx + uy * Fy + uz * Fz;
-    // d[r] = s_r (m_r - meq_r) - (1 - s_r/2) Fm_r
-    float d[Q];
-    const float he = 1.0f - 0.5f * s.se, hps = 1.0f - 0.5f * s.seps;
-    const float hq = 1.0f - 0.5f * s.sq, hn = 1.0f - 0.5f * s.snu;
-    d[0] = 0.0f;
+    constexpr float inv = 1.0f / (float)tnorm<DIM>(R);
+    float a = 0.0f;
     if constexpr (DIM == 2) {
-        d[1] = s.se * (m[1] - rho * (-2.0f + 3.0f * uu)) - he * (6.0f * uF);
-        d[2] = s.seps * (m[2] - rho * (1.0f - 3.0f * uu)) - hps * (-6.0f * uF);
-        d[3] = (J[0] - rho * ux) - 0.5f * Fx;
-        d[4] = s.sq * (m[4] + rho * ux) - hq * (-Fx);
-        d[5] = (J[1] - rho * uy) - 0.5f * Fy;
-        d[6] = s.sq * (m[6] + rho * uy) - hq * (-Fy);
-        d[7] = s.snu * (m[7] - rho * (ux * ux - uy * uy)) - hn * (2.0f * (ux * Fx - uy * Fy));
-        d[8] = s.snu * (m[8] - rho * ux * uy) - hn * (ux * Fy + uy * Fx);
+        if constexpr (R == 1) a = s.se * (m - rho * (-2.0f + 3.0f * uu)) - (1.0f - 0.5f * s.se) * (6.0f * uF);
+        else if constexpr (R == 2) a = s.seps * (m - rho * (1.0f - 3.0f * uu)) + (1.0f - 0.5f * s.seps) * (6.0f * uF);
+        else if constexpr (R == 3) a = (J[0] - rho * ux) - 0.5f * Fx;
+        else if constexpr (R == 4) a = s.sq * (m + rho * ux) + (1.0f - 0.5f * s.sq) * Fx;
+        else if constexpr (R == 5) a = (J[1] - rho * uy) - 0.5f * Fy;
+        else if constexpr (R == 6) a = s.sq * (m + rho * uy) + (1.0f - 0.5f * s.sq) * Fy;
+        else if constexpr (R == 7)
+            a = s.snu * (m - rho * (ux * ux - uy * uy)) - (1.0f - 0.5f * s.snu) * (2.0f * (ux * Fx - uy * Fy));
+        else if constexpr (R == 8) a = s.snu * (m - rho * ux * uy) - (1.0f - 0.5f * s.snu) * (ux * Fy + uy * Fx);
     } else {
-        const float c23 = 2.0f / 3.0f;
-        const float pxx = 3.0f * ux * ux - uu, pww = uy * uy - uz * uz;
-        const float fxx = 3.0f * ux * Fx - uF, fww = uy * Fy - uz * Fz;
-        d[1] = s.se * (m[1] - rho * (-11.0f + 19.0f * uu)) - he * (38.0f * uF);
-        d[2] = s.seps * (m[2] - rho * (3.0f - 5.5f * uu)) - hps * (-11.0f * uF);
-        d[3] = (J[0] - rho * ux) - 0.5f * Fx;
-        d[4] = s.sq * (m[4] + c23 * rho * ux) - hq * (-c23 * Fx);
-        d[5] = (J[1] - rho * uy) - 0.5f * Fy;
-        d[6] = s.sq * (m[6] + c23 * rho * uy) - hq * (-c23 * Fy);
-        d[7] = (J[2] - rho * uz) - 0.5f * Fz;
-        d[8] = s.sq * (m[8] + c23 * rho * uz) - hq * (-c23 * Fz);
-        d[9] = s.snu * (m[9] - rho * pxx) - hn * (2.0f * fxx);
-        d[10] = s.snu * (m[10] + 0.5f * rho * pxx) - hn * (-fxx);
-        d[11] = s.snu * (m[11] - rho * pww) - hn * (2.0f * fww);
-        d[12] = s.snu * (m[12] + 0.5f * rho * pww) - hn * (-fww);
-        d[13] = s.snu * (m[13] - rho * ux * uy) - hn * (ux * Fy + uy * Fx);
-        d[14] = s.snu * (m[14] - rho * uy * uz) - hn * (uy * Fz + uz * Fy);
-        d[15] = s.snu * (m[15] - rho * ux * uz) - hn * (ux * Fz + uz * Fx);
-        d[16] = s.sq * m[16];
-        d[17] = s.sq * m[17];
-        d[18] = s.sq * m[18];
+        constexpr float c23 = 2.0f / 3.0f;
+        if constexpr (R == 1) a = s.se * (m - rho * (-11.0f + 19.0f * uu)) - (1.0f - 0.5f * s.se) * (38.0f * uF);
+        else if constexpr (R == 2) a = s.seps * (m - rho * (3.0f - 5.5f * uu)) + (1.0f - 0.5f * s.seps) * (11.0f * uF);
+        else if constexpr (R == 3) a = (J[0] - rho * ux) - 0.5f * Fx;
+        else if constexpr (R == 4) a = s.sq * (m + c23 * rho * ux) + (1.0f - 0.5f * s.sq) * (c23 * Fx);
+        else if constexpr (R == 5) a = (J[1] - rho * uy) - 0.5f * Fy;
+        else if constexpr (R == 6) a = s.sq * (m + c23 * rho * uy) + (1.0f - 0.5f * s.sq) * (c23 * Fy);
+        else if constexpr (R == 7) a = (J[2] - rho * uz) - 0.5f * Fz;
+        else if constexpr (R == 8) a = s.sq * (m + c23 * rho * uz) + (1.0f - 0.5f * s.sq) * (c23 * Fz);
+        else if constexpr (R == 9)
+            a = s.snu * (m - rho * (3.0f * ux * ux - uu)) - (1.0f - 0.5f * s.snu) * (2.0f * (3.0f * ux * Fx - uF));
+        else if constexpr (R == 10)
+            a = s.snu * (m + 0.5f * rho * (3.0f * ux * ux - uu)) + (1.0f - 0.5f * s.snu) * (3.0f * ux * Fx - uF);
+        else if constexpr (R == 11)
+            a = s.snu * (m - rho * (uy * uy - uz * uz)) - (1.0f - 0.5f * s.snu) * (2.0f * (uy * Fy - uz * Fz));
+        else if constexpr (R == 12)
+            a = s.snu * (m + 0.5f * rho * (uy * uy - uz * uz)) + (1.0f - 0.5f * s.snu) * (uy * Fy - uz * Fz);
+        else if constexpr (R == 13) a = s.snu * (m - rho * ux * uy) - (1.0f - 0.5f * s.snu) * (ux * Fy + uy * Fx);
+        else if constexpr (R == 14) a = s.snu * (m - rho * uy * uz) - (1.0f - 0.5f * s.snu) * (uy * Fz + uz * Fy);
+        else if constexpr (R == 15) a = s.snu * (m - rho * ux * uz) - (1.0f - 0.5f * s.snu) * (ux * Fz + uz * Fx);
+        else a = s.sq * m;   // m_x, m_y, m_z: no equilibrium or forcing part
     }
-#pragma unroll
-    for (int r = 1; r < Q; r++) d[r] *= 1.0f / (float)tnorm<DIM>(r);
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        float acc = f[i];
-#pragma unroll
-        for (int r = 1; r < Q; r++) {
-            const int t = trow<DIM>(r, i);
-            if (t == 1) acc -= d[r];
-            else if (t == -1) acc += d[r];
-            else if (t != 0) acc = fmaf(-(float)t, d[r], acc);
+    return a * inv;
+}
+
+// eq. (1) in moment space on a node in pair form; writes f* into out[Q].
+// Rows are streamed: each moment is formed, relaxed and scattered back into
+// the even / odd parts of the pairs before the next one.
+template <int DIM>
+__device__ __forceinline__ void collide_pairs(const PairF<DIM> &q, float rho, const float (&J)[3],
+                                              const float (&u)[3], const float (&F)[3], const Rates &s,
+                                              float (&out)[Lat<DIM>::Q])
+{
+    constexpr int Q = Lat<DIM>::Q;
+    constexpr int P = Pairs<DIM>::P;
+    const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    float ev[P], od[P], rest = 0.0f;
+    static_for<P>([&](auto pc) {
+        ev[decltype(pc)::value] = 0.0f;
+        od[decltype(pc)::value] = 0.0f;
+    });
+    static_for<Q - 1>([&](auto rc) {
+        constexpr int R = decltype(rc)::value + 1;
+        constexpr bool odd = row_odd<DIM>(R);
+        constexpr bool mom = DIM == 2 ? (R == 3 || R == 5) : (R == 3 || R == 5 || R == 7);
+        float m = 0.0f;
+        if constexpr (!mom) {
+            constexpr int t0 = trow<DIM>(R, 0);
+            if constexpr (t0 != 0) m = (float)t0 * q.f0;
+            static_for<P>([&](auto pc) {
+                constexpr int p = decltype(pc)::value;
+                constexpr int t = trow<DIM>(R, Pairs<DIM>::first(p));
+                const float v = odd ? q.d[p] : q.s[p];
+                if constexpr (t == 1) m += v;
+                else if constexpr (t == -1) m -= v;
+                else if constexpr (t != 0) m = fmaf((float)t, v, m);
+            });
         }
-        f[i] = acc;
-    }
+        const float a = relax_row<DIM, R>(m, rho, J, u, F, s, uu, uF);
+        constexpr int t0 = trow<DIM>(R, 0);
+        if constexpr (t0 != 0) rest = fmaf((float)t0, a, rest);
+        static_for<P>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            constexpr int t = trow<DIM>(R, Pairs<DIM>::first(p));
+            if constexpr (t != 0) {
+                float &acc = odd ? od[p] : ev[p];
+                if constexpr (t == 1) acc += a;
+                else if constexpr (t == -1) acc -= a;
+                else acc = fmaf((float)t, a, acc);
+            }
+        });
+    });
+    out[0] = q.f0 - rest;
+    static_for<P>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = Pairs<DIM>::first(p), o = Lat<DIM>::OPP[i];
+        const float fi = 0.5f * (q.s[p] + q.d[p]), fo = 0.5f * (q.s[p] - q.d[p]);
+        out[i] = fi - ev[p] - od[p];
+        out[o] = fo - ev[p] + od[p];
+    });
 }
 
 // Equilibrium of eq. (6) (second-order term over 2 cs^4), cs^2 = 1/3.

@@ -20,8 +20,10 @@ using namespace lbm;
 
 namespace {
 
-constexpr int TX2 = 64, TY2 = 8;            // D2Q9 tile
-constexpr int TX3 = 32, TY3 = 8, TZ3 = 4;   // D3Q19 tile
+// Sweep tiles of the node update: lateral tile, planes per iteration W and
+// planes per block ZC along the sweep axis (y in 2-D, z in 3-D).
+constexpr int TX2 = 64, W2 = 4, ZC2 = 16;
+constexpr int TX3 = 32, TY3 = 8, W3 = 4, ZC3 = 16;
 constexpr size_t ALIGN = 256;
 
 thread_local std::string g_create_error;
@@ -31,15 +33,16 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     int dim = 0, Q = 0, storage = 0;
     Geometry g{};
-    int tiles[3] = {1, 1, 1};
-    int64_t nblocks_main = 0;
+    int tiles[3] = {1, 1, 1};      // lateral x tiles, lateral y tiles, sweep chunks
+    int64_t nblocks_main = 0;      // work items of the node update
+    int64_t grid_main = 0;         // launched blocks (a multiple of 8)
     int64_t n_slots = 0, n_in = 0, n_out = 0;
     int nb_in = 0, nb_out = 0;
     int nb_mass = 0;
     bool boundary = false;
     // byte offsets into the workspace
     size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
-        o_flag, o_mpart, o_mout, total;
+        o_flag, o_mpart, o_mout, o_patch, total;
 };
 
 // Host-side static maps built from the configuration.
@@ -105,6 +108,12 @@ std::string build_maps(const lbm_config *c, Maps &m)
     }
     const int64_t N = (int64_t)c->n[0] * c->n[1] * nz;
     const int Q = lat_Q(c->dim);
+    {
+        // each component array is addressed with 32-bit byte offsets
+        const int64_t pad = (int64_t)(c->n[0] + 2) * (c->n[1] + 2) * (c->dim == 3 ? c->n[2] + 2 : 1);
+        const int64_t bytes = pad * Q * (c->storage == LBM_STORE_F32 ? 4 : 2);
+        if (bytes >= ((int64_t)1 << 31)) return "domain too large for one context (2 GiB per component array)";
+    }
     m.type.assign(N, 0);
     m.bslot.assign(N, -1);
     m.in.clear();
@@ -251,14 +260,15 @@ Layout make_layout(const lbm_config *c, const Maps &m)
     g.Ppad = (int64_t)g.P[0] * g.P[1] * g.P[2];
     if (c->dim == 2) {
         L.tiles[0] = (g.n[0] + TX2 - 1) / TX2;
-        L.tiles[1] = (g.n[1] + TY2 - 1) / TY2;
-        L.tiles[2] = 1;
+        L.tiles[1] = 1;
+        L.tiles[2] = (g.n[1] + ZC2 - 1) / ZC2;
     } else {
         L.tiles[0] = (g.n[0] + TX3 - 1) / TX3;
         L.tiles[1] = (g.n[1] + TY3 - 1) / TY3;
-        L.tiles[2] = (g.n[2] + TZ3 - 1) / TZ3;
+        L.tiles[2] = (g.n[2] + ZC3 - 1) / ZC3;
     }
     L.nblocks_main = (int64_t)L.tiles[0] * L.tiles[1] * L.tiles[2];
+    L.grid_main = (L.nblocks_main + 7) / 8 * 8;
     L.n_in = (int64_t)m.in.size();
     L.n_out = (int64_t)m.out.size();
     L.n_slots = 0;
@@ -284,6 +294,7 @@ Layout make_layout(const lbm_config *c, const Maps &m)
     L.o_flag = take(4);
     L.o_mpart = take((size_t)L.nb_mass * 16);
     L.o_mout = take(16);
+    L.o_patch = take(sizeof(Patch) * MAX_PATCH);
     L.total = o;
     return L;
 }
@@ -327,22 +338,24 @@ lbm_status fail(lbm_ctx *c, lbm_status st, const std::string &msg)
 template <int DIM, int STORE> struct Launch {
     using T = typename Codec<STORE>::T;
     static constexpr int TX = DIM == 2 ? TX2 : TX3;
-    static constexpr int TY = DIM == 2 ? TY2 : TY3;
-    static constexpr int TZ = DIM == 2 ? 1 : TZ3;
+    static constexpr int TY = DIM == 2 ? 1 : TY3;
+    static constexpr int W = DIM == 2 ? W2 : W3;
+    static constexpr int ZC = DIM == 2 ? ZC2 : ZC3;
 
     static void main_kernel(lbm_ctx *c, int mode, double *orho, double *ou)
     {
         const Layout &L = c->L;
         Boundary bd = c->bd;
         if (mode == MODE_MOMENTS) bd.qpart = nullptr;
+        const int items = (int)L.nblocks_main;
         if (mode == MODE_STEP)
-            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_STEP, TX, TY, TZ>), dim3((unsigned)L.nblocks_main), dim3(256), 0,
-                               c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->ph, bd,
-                               L.tiles[0], L.tiles[1], orho, ou, c->flag());
+            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_STEP, TX, TY, W, ZC>), dim3((unsigned)L.grid_main), dim3(256),
+                               0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->ph, bd,
+                               L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
         else
-            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_MOMENTS, TX, TY, TZ>), dim3((unsigned)L.nblocks_main), dim3(256), 0,
-                               c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->ph, bd,
-                               L.tiles[0], L.tiles[1], orho, ou, c->flag());
+            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_MOMENTS, TX, TY, W, ZC>), dim3((unsigned)L.grid_main),
+                               dim3(256), 0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->ph,
+                               bd, L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
     }
 
     // ev (optional): 8 events bracketing the four launches of the step
@@ -479,14 +492,15 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
 
     Boundary &bd = c->bd;
     bd.n_patch = cfg->n_inlets;
+    Patch patches[MAX_PATCH] = {};
     for (int q = 0; q < cfg->n_inlets; q++) {
         const lbm_inlet &p = cfg->inlets[q];
-        bd.patch[q].axis = p.axis;
-        bd.patch[q].sign = p.side == 0 ? 1 : -1;
-        bd.patch[q].rho[0] = (float)p.rho[0];
-        bd.patch[q].rho[1] = (float)p.rho[1];
-        bd.patch[q].u_n = (float)p.u_n;
-        bd.patch[q].alpha_on = p.alpha_on ? 1 : 0;
+        patches[q].axis = p.axis;
+        patches[q].sign = p.side == 0 ? 1 : -1;
+        patches[q].rho[0] = (float)p.rho[0];
+        patches[q].rho[1] = (float)p.rho[1];
+        patches[q].u_n = (float)p.u_n;
+        patches[q].alpha_on = p.alpha_on ? 1 : 0;
     }
     bd.has_outlet = cfg->has_outlet ? 1 : 0;
     bd.chi_on = cfg->has_outlet && cfg->outlet.chi_on ? 1 : 0;
@@ -505,6 +519,7 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
     bd.ucpart = (double *)(ws + L.o_ucpart);
     bd.n_ucpart = L.nb_out;
     bd.scal = (double *)(ws + L.o_scal);
+    bd.patch = (const Patch *)(ws + L.o_patch);
 
     auto st = [&]() -> lbm_status {
         hipStream_t s = c->stream;
@@ -515,6 +530,7 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
             HIPCHECK(c, hipMemcpyAsync(ws + L.o_in, m.in.data(), m.in.size() * sizeof(InletRec), hipMemcpyHostToDevice, s));
         if (L.n_out)
             HIPCHECK(c, hipMemcpyAsync(ws + L.o_out, m.out.data(), m.out.size() * sizeof(OutletRec), hipMemcpyHostToDevice, s));
+        HIPCHECK(c, hipMemcpyAsync(ws + L.o_patch, patches, sizeof patches, hipMemcpyHostToDevice, s));
         const double one = 1.0;
         HIPCHECK(c, hipMemcpyAsync(ws + L.o_scal + SC_CHI * 8, &one, 8, hipMemcpyHostToDevice, s));
         // initial state f = feq(rho0, u0), scattered into the source slots

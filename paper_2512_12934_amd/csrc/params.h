@@ -59,7 +59,7 @@ struct Patch {
 
 struct Boundary {
     int n_patch;
-    Patch patch[MAX_PATCH];
+    const Patch *patch;       // [n_patch] device copy of the inlet patches
     int has_outlet, chi_on;
     int out_axis, out_sign;   // outward normal = out_sign * e_axis
     int n_in, n_out;          // record counts
