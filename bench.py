@@ -87,15 +87,20 @@ def main():
     kms = sim.time_kernels(args.steps)
     bf = 4 if args.storage == "f32" else 2
     Q = 19
-    b_alg = 2 * Q * 2 * bf            # bytes per fluid node per step
-    achieved = fluid * b_alg / (kms[0] / 1e3) / 1e9
+    b_alg = 2 * Q * 2 * bf            # bytes per fluid node per step: read and write every population once
+    two_pass = kms[4] > 0
+    # the node update alone: every population read and written once, plus the
+    # 8-byte psi pair of the node in the two-pass mode
+    b_main = b_alg + (8 if two_pass else 0)
+    achieved = fluid * b_main / (kms[0] / 1e3) / 1e9
     step_gbs = fluid * b_alg / (ms_step / 1e3) / 1e9
     flux = sim.mass_flux()
     finite = bool(np.isfinite(flux["mass"]).all())
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "k_main<3,%d>" % (0 if args.storage == "f32" else 1),
-            "kernel_ms": round(kms[0], 5), "bytes_per_node": b_alg, "nodes_per_launch": fluid}
+            "kernel_ms": round(kms[0], 5), "bytes_per_node": b_main, "nodes_per_launch": fluid,
+            "mode": "two-pass (k_psi + k_main)" if two_pass else "fused (k_main only)"}
     del sim
     torch.cuda.empty_cache()
 
@@ -158,7 +163,7 @@ def main():
         "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
         "roofline": roof,
         "cpu_baseline": cpu,
-        "kernel_ms": {"main": kms[0], "outlet": kms[1], "inlet": kms[2], "outlet_fill": kms[3]},
+        "kernel_ms": {"main": kms[0], "psi": kms[4], "outlet": kms[1], "inlet": kms[2], "outlet_fill": kms[3]},
         "finite": finite,
         "extra": extra,
     }

@@ -144,9 +144,10 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *f_host, size_t bytes);
 
 /* Measurement hook: enqueues n steps like lbm_step, bracketing every kernel
  * launch with HIP events on the context stream, then synchronises and writes
- * the mean duration in milliseconds of each launch kind into ms[4]:
- * [0] the fused node update, [1] the outlet collision, [2] the inlet
- * reconstruction, [3] the outlet fill (0 where a kind is not launched). */
+ * the mean duration in milliseconds of each launch kind into ms[5]:
+ * [0] the node update, [1] the outlet collision, [2] the inlet
+ * reconstruction, [3] the outlet fill, [4] the density pass that precedes
+ * the node update in the two-pass mode (0 where a kind is not launched). */
 lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *ms);
 
 /* Number of steps taken; the stream is not synchronised. */

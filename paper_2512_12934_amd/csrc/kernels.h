@@ -9,10 +9,13 @@
 //     f_i(x, t+1) = padding slot at x - e_i if that lies beyond an open face
 // Two arrays alternate between source and destination every step.
 //
-// One step is four launches:
+// One step is four (fused mode) or five (two-pass mode) launches:
+//   k_psi            (two-pass mode) psi_k = rho_k of every node into an array
 //   k_main           all fluid nodes, swept along the last axis: densities of
 //                    each plane plus a two-node lateral halo into an LDS ring
-//                    (mirror ghost layers at open faces, eqs. 24-25), force
+//                    (from the psi array, or recomputed from the populations
+//                    in the fused mode; mirror ghost layers at open faces,
+//                    eqs. 24-25), force
 //                    (eqs. 10-11), common velocity (eqs. 7-8), MRT collision
 //                    (eq. 1); FP64 partial mass flows at inlet nodes and the
 //                    x_{N-1} column (eq. 23)
@@ -227,10 +230,15 @@ enum { MODE_STEP = 0, MODE_MOMENTS = 1 };
 // each of the eight XCDs takes a contiguous range of them, so the blocks that
 // share halo data share an L2.
 // ---------------------------------------------------------------------------
-template <int DIM, int STORE, int MODE, int TX, int TY, int W, int ZC>
+//
+// PSRC selects where psi comes from: 0 = recomputed here from the gathered
+// populations of each plane (one fused kernel), 1 = read from the psi array
+// that k_psi wrote for this step (the populations are then read only once).
+template <int DIM, int STORE, int MODE, int PSRC, int TX, int TY, int W, int ZC>
 __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__restrict__ src,
                                               typename Codec<STORE>::T *__restrict__ dst,
-                                              const uint32_t *__restrict__ type, Geometry g, Physics ph,
+                                              const uint32_t *__restrict__ type,
+                                              const float2 *__restrict__ psi, Geometry g, Physics ph,
                                               Boundary bd, int tiles_x, int tiles_y, int n_items,
                                               double *__restrict__ out_rho, double *__restrict__ out_u,
                                               int *__restrict__ flag)
@@ -273,6 +281,23 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                 if (DIM == 3) { gy = y0 - 2 + ly; gz = pl; }
                 else { gy = pl; gz = 0; }
                 const bool need = gx < g.n[0] + 2 && gy < g.n[1] + 2 && (DIM == 2 || gz < g.n[2] + 2);
+                const int slot = ((pl + 4 * R) & (R - 1)) * PLANE + r;
+                if constexpr (PSRC == 1) {
+                    // psi of this step from k_psi; solids carry -0.0 (zero in
+                    // every sum, and the sign marks them for the adhesion stencil)
+                    float2 v = make_float2(0.0f, 0.0f);
+                    uint8_t sol = 1;
+                    if (need) {
+                        gx = map_axis(gx, g.n[0], g.periodic[0]);
+                        gy = map_axis(gy, g.n[1], g.periodic[1]);
+                        if (DIM == 3) gz = map_axis(gz, g.n[2], g.periodic[2]);
+                        v = psi[(int64_t)gx + (int64_t)g.n[0] * ((int64_t)gy + (int64_t)g.n[1] * gz)];
+                        sol = signbit(v.x) ? 1 : 0;
+                    }
+                    s_psi[slot] = v;
+                    s_sol[slot] = sol;
+                    continue;
+                }
                 uint32_t tw = T_SOLID;
                 uint32_t pp = 0;
                 if (need) {
@@ -293,7 +318,6 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                     bgather<DIM, STORE>(rs1, g, pp, tw, gx, gy, gz, wave_fast, f);
                     static_for<Q>([&](auto ic) { p2 += f[decltype(ic)::value]; });
                 }
-                const int slot = ((pl + 4 * R) & (R - 1)) * PLANE + r;
                 s_psi[slot] = make_float2(p1, p2);
                 s_sol[slot] = fluid ? 0 : 1;
             }
@@ -484,6 +508,38 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
             bd.qpart[2 * item + 1] = q_out;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// k_psi: psi_k = rho_k = sum_i f_i^k of every node (eq. 8 with psi_k = rho_k)
+// from the post-streaming populations, as float2 per box node; solid nodes
+// get (-0.0, -0.0).
+// ---------------------------------------------------------------------------
+template <int DIM, int STORE>
+__global__ __launch_bounds__(256) void k_psi(const typename Codec<STORE>::T *__restrict__ src,
+                                             const uint32_t *__restrict__ type, Geometry g,
+                                             float2 *__restrict__ psi)
+{
+    constexpr int Q = Lat<DIM>::Q;
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = b < g.N;
+    const uint32_t tw = valid ? type[b] : T_SOLID;
+    const bool fluid = !(tw & T_SOLID);
+    const bool wave_fast = __ballot(fluid && (tw & (T_BBMASK | T_EDGE))) == 0;
+    if (!valid) return;
+    if (!fluid) {
+        psi[b] = make_float2(-0.0f, -0.0f);
+        return;
+    }
+    int x, y, z;
+    coords_of(g, b, x, y, z);
+    const uint32_t p = (uint32_t)pidx(g, x, y, DIM == 3 ? z : -1);
+    float f[Q], r1 = 0.0f, r2 = 0.0f;
+    bgather<DIM, STORE>(comp_rsrc<STORE>(src, 0, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f);
+    static_for<Q>([&](auto ic) { r1 += f[decltype(ic)::value]; });
+    bgather<DIM, STORE>(comp_rsrc<STORE>(src, 1, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f);
+    static_for<Q>([&](auto ic) { r2 += f[decltype(ic)::value]; });
+    psi[b] = make_float2(r1, r2);
 }
 
 // chi of eq. (23); undefined (no outflow through x_{N-1}, or flow against the

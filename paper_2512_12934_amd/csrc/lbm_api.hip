@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -42,7 +43,8 @@ struct Layout {
     bool boundary = false;
     // byte offsets into the workspace
     size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
-        o_flag, o_mpart, o_mout, o_patch, total;
+        o_flag, o_mpart, o_mout, o_patch, o_psi, total;
+    int psi_mode = 1;              // 1: psi array written by k_psi, 0: recomputed in k_main
 };
 
 // Host-side static maps built from the configuration.
@@ -295,6 +297,11 @@ Layout make_layout(const lbm_config *c, const Maps &m)
     L.o_mpart = take((size_t)L.nb_mass * 16);
     L.o_mout = take(16);
     L.o_patch = take(sizeof(Patch) * MAX_PATCH);
+    {
+        const char *env = getenv("LBM_PSI_MODE");
+        L.psi_mode = env ? (atoi(env) != 0 ? 1 : 0) : 1;
+    }
+    L.o_psi = take(L.psi_mode ? (size_t)g.N * 8 : 1);
     L.total = o;
     return L;
 }
@@ -342,46 +349,65 @@ template <int DIM, int STORE> struct Launch {
     static constexpr int W = DIM == 2 ? W2 : W3;
     static constexpr int ZC = DIM == 2 ? ZC2 : ZC3;
 
-    static void main_kernel(lbm_ctx *c, int mode, double *orho, double *ou)
+    // ev (optional): events bracketing k_psi (ev[8], ev[9]) and k_main (ev[0], ev[1])
+    static void main_kernel(lbm_ctx *c, int mode, double *orho, double *ou, hipEvent_t *ev = nullptr)
     {
         const Layout &L = c->L;
         Boundary bd = c->bd;
         if (mode == MODE_MOMENTS) bd.qpart = nullptr;
         const int items = (int)L.nblocks_main;
+        const float2 *psi = (const float2 *)(c->ws + L.o_psi);
+        if (L.psi_mode) {
+            if (ev) (void)hipEventRecord(ev[8], c->stream);
+            hipLaunchKernelGGL((k_psi<DIM, STORE>), dim3((unsigned)((L.g.N + 255) / 256)), dim3(256), 0, c->stream,
+                               (const T *)c->fsrc(), c->type(), L.g, (float2 *)psi);
+            if (ev) (void)hipEventRecord(ev[9], c->stream);
+            if (ev) (void)hipEventRecord(ev[0], c->stream);
+            if (mode == MODE_STEP)
+                hipLaunchKernelGGL((k_main<DIM, STORE, MODE_STEP, 1, TX, TY, W, ZC>), dim3((unsigned)L.grid_main),
+                                   dim3(256), 0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), psi, L.g,
+                                   c->ph, bd, L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
+            else
+                hipLaunchKernelGGL((k_main<DIM, STORE, MODE_MOMENTS, 1, TX, TY, W, ZC>), dim3((unsigned)L.grid_main),
+                                   dim3(256), 0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), psi, L.g,
+                                   c->ph, bd, L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
+            if (ev) (void)hipEventRecord(ev[1], c->stream);
+            return;
+        }
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
         if (mode == MODE_STEP)
-            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_STEP, TX, TY, W, ZC>), dim3((unsigned)L.grid_main), dim3(256),
-                               0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->ph, bd,
+            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_STEP, 0, TX, TY, W, ZC>), dim3((unsigned)L.grid_main), dim3(256),
+                               0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), psi, L.g, c->ph, bd,
                                L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
         else
-            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_MOMENTS, TX, TY, W, ZC>), dim3((unsigned)L.grid_main),
-                               dim3(256), 0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->ph,
-                               bd, L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
+            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_MOMENTS, 0, TX, TY, W, ZC>), dim3((unsigned)L.grid_main),
+                               dim3(256), 0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), psi, L.g,
+                               c->ph, bd, L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
 
-    // ev (optional): 8 events bracketing the four launches of the step
+    // ev (optional): 10 events bracketing the launches of the step
     static void step(lbm_ctx *c, hipEvent_t *ev = nullptr)
     {
         const Layout &L = c->L;
-        if (ev) hipEventRecord(ev[0], c->stream);
-        main_kernel(c, MODE_STEP, nullptr, nullptr);
-        if (ev) hipEventRecord(ev[1], c->stream);
+        main_kernel(c, MODE_STEP, nullptr, nullptr, ev);
         if (L.boundary) {
             const unsigned nb = (unsigned)std::max(L.nb_out, 1);
-            if (ev) hipEventRecord(ev[2], c->stream);
+            if (ev) (void)hipEventRecord(ev[2], c->stream);
             hipLaunchKernelGGL((k_outlet<DIM, STORE>), dim3(nb), dim3(256), 0, c->stream, (const T *)c->fsrc(),
                                (T *)c->fdst(), c->type(), L.g, c->ph, c->bd, c->flag());
-            if (ev) hipEventRecord(ev[3], c->stream);
+            if (ev) (void)hipEventRecord(ev[3], c->stream);
             if (L.nb_in + L.nb_out > 0) {
-                if (ev) hipEventRecord(ev[4], c->stream);
+                if (ev) (void)hipEventRecord(ev[4], c->stream);
                 hipLaunchKernelGGL((k_inlet<DIM, STORE>), dim3((unsigned)(L.nb_in + L.nb_out)), dim3(256), 0,
                                    c->stream, (T *)c->fdst(), c->type(), L.g, c->bd, L.nb_in);
-                if (ev) hipEventRecord(ev[5], c->stream);
+                if (ev) (void)hipEventRecord(ev[5], c->stream);
             }
             if (L.nb_out > 0) {
-                if (ev) hipEventRecord(ev[6], c->stream);
+                if (ev) (void)hipEventRecord(ev[6], c->stream);
                 hipLaunchKernelGGL((k_outlet_fill<DIM, STORE>), dim3((unsigned)L.nb_out), dim3(256), 0, c->stream,
                                    (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->bd);
-                if (ev) hipEventRecord(ev[7], c->stream);
+                if (ev) (void)hipEventRecord(ev[7], c->stream);
             }
         }
         c->cur ^= 1;
@@ -655,21 +681,21 @@ lbm_status lbm_time_kernels(lbm_ctx *c, int64_t n, double *ms)
 {
     if (!c || n <= 0 || !ms) return fail(c, LBM_EINVAL, "bad arguments to lbm_time_kernels");
     if (c->unstable) return fail(c, LBM_ESTATE, "context flagged unstable");
-    const int64_t total = n * 8;
+    const int64_t total = n * 10;
     std::vector<hipEvent_t> ev(total);
     for (auto &e : ev) HIPCHECK(c, hipEventCreate(&e));
-    for (int64_t t = 0; t < n; t++) dispatch(c, [&](auto l) { decltype(l)::step(c, ev.data() + 8 * t); });
+    for (int64_t t = 0; t < n; t++) dispatch(c, [&](auto l) { decltype(l)::step(c, ev.data() + 10 * t); });
     HIPCHECK(c, hipGetLastError());
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     c->steps += n;
-    const bool used[4] = {true, c->L.boundary, c->L.boundary && c->L.nb_in + c->L.nb_out > 0,
-                          c->L.boundary && c->L.nb_out > 0};
-    for (int k = 0; k < 4; k++) {
+    const bool used[5] = {true, c->L.boundary, c->L.boundary && c->L.nb_in + c->L.nb_out > 0,
+                          c->L.boundary && c->L.nb_out > 0, c->L.psi_mode != 0};
+    for (int k = 0; k < 5; k++) {
         double acc = 0.0;
         if (used[k])
             for (int64_t t = 0; t < n; t++) {
                 float v = 0.0f;
-                HIPCHECK(c, hipEventElapsedTime(&v, ev[8 * t + 2 * k], ev[8 * t + 2 * k + 1]));
+                HIPCHECK(c, hipEventElapsedTime(&v, ev[10 * t + 2 * k], ev[10 * t + 2 * k + 1]));
                 acc += v;
             }
         ms[k] = used[k] ? acc / (double)n : 0.0;

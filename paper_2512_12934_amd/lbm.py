@@ -213,8 +213,9 @@ class LBM:
 
     def time_kernels(self, n):
         """Run n steps with HIP events around every launch; mean ms of
-        (node update, outlet collision, inlet reconstruction, outlet fill)."""
-        ms = (C.c_double * 4)()
+        (node update, outlet collision, inlet reconstruction, outlet fill,
+        density pass)."""
+        ms = (C.c_double * 5)()
         self._check(lib().lbm_time_kernels(self._h, int(n), ms))
         return list(ms)
 
