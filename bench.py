@@ -56,7 +56,7 @@ def main():
         a = torch.ones(n, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
         for _ in range(5):
-            b.copy_(a)
+            torch.mul(a, 2.0, out=b)      # one elementwise kernel: reads a, writes b
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}), flush=True)
         return

@@ -88,6 +88,9 @@ typedef struct {
     lbm_inlet inlets[LBM_MAX_INLETS];
     int has_outlet;
     lbm_outlet outlet;
+    int tile_config;         /* node-update configuration, -1 = library default
+                                (an index into the tuning space; the autotuner
+                                measures them) */
     const uint8_t *solid;    /* [N], 1 = solid; every fluid node on a
                                 non-periodic face must belong to a patch */
     const double *rho0;      /* [2][N] initial component densities (> 0 on fluid) */
@@ -149,6 +152,11 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *f_host, size_t bytes);
  * reconstruction, [3] the outlet fill, [4] the density pass that precedes
  * the node update in the two-pass mode (0 where a kind is not launched). */
 lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *ms);
+
+/* Number of node-update configurations of the tuning space for dim (2 or 3),
+ * valid values of lbm_config.tile_config being -1 .. count-1; 0 for any other
+ * dim.  Every configuration computes the same arithmetic per node. */
+int lbm_tile_configs(int dim);
 
 /* Number of steps taken; the stream is not synchronised. */
 int64_t lbm_steps_done(const lbm_ctx *ctx);

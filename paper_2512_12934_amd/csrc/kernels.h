@@ -17,8 +17,8 @@
 //                    in the fused mode; mirror ghost layers at open faces,
 //                    eqs. 24-25), force
 //                    (eqs. 10-11), common velocity (eqs. 7-8), MRT collision
-//                    (eq. 1); FP64 partial mass flows at inlet nodes and the
-//                    x_{N-1} column (eq. 23)
+//                    (eq. 1); FP64 mass flow rho u.n of every inlet node and
+//                    x_{N-1} node into its face slot (eq. 23)
 //   k_outlet         chi = Q_in / Q' (eq. 23) and the collision of the outlet
 //                    column with the corrected normal velocity (eq. 22)
 //   k_inlet          alpha-corrected NEQ extrapolation (eqs. 13-19) into the
@@ -95,9 +95,11 @@ __device__ __forceinline__ int e_axis(int i, int a)
     return a == 0 ? Lat<DIM>::E[i][0] : (a == 1 ? Lat<DIM>::E[i][1] : Lat<DIM>::E[i][2]);
 }
 
+// Padded index of box node (x, y, z); x = 0 sits XOFF elements into each row
+// so that rows start on a 128-byte line (see Geometry).
 __device__ __forceinline__ int64_t pidx(const Geometry &g, int x, int y, int z)
 {
-    return (int64_t)(x + 1) + (int64_t)g.P[0] * ((int64_t)(y + 1) + (int64_t)g.P[1] * (int64_t)(z + 1));
+    return (int64_t)(x + XOFF) + (int64_t)g.P[0] * ((int64_t)(y + 1) + (int64_t)g.P[1] * (int64_t)(z + 1));
 }
 
 template <int DIM>
@@ -217,7 +219,6 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
     block_sum2(a, b, red);
 }
 
-enum { MODE_STEP = 0, MODE_MOMENTS = 1 };
 
 // ---------------------------------------------------------------------------
 // k_main: the fused per-node update as a sweep along the last lattice axis
@@ -234,7 +235,11 @@ enum { MODE_STEP = 0, MODE_MOMENTS = 1 };
 // PSRC selects where psi comes from: 0 = recomputed here from the gathered
 // populations of each plane (one fused kernel), 1 = read from the psi array
 // that k_psi wrote for this step (the populations are then read only once).
-template <int DIM, int STORE, int MODE, int PSRC, int TX, int TY, int W, int ZC>
+//
+// KEEPB = 1 holds both components' populations in registers between the
+// velocity and the collision; KEEPB = 0 gathers component 2 again after
+// component 1 is stored (fewer registers, one more pass through the caches).
+template <int DIM, int STORE, int MODE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
 __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__restrict__ src,
                                               typename Codec<STORE>::T *__restrict__ dst,
                                               const uint32_t *__restrict__ type,
@@ -251,15 +256,12 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
     constexpr int NPT = DIM == 3 ? W : 1;          // nodes per thread per iteration
     constexpr int NOFF = DIM == 3 ? 125 : 25;      // offsets of the 5^DIM stencil box
     static_assert(DIM == 3 ? TX * LY == 256 : TX * W == 256, "256 threads per block");
-    static_assert((R & (R - 1)) == 0, "ring size must be a power of two");
     __shared__ float2 s_psi[R * PLANE];
     __shared__ uint8_t s_sol[R * PLANE];
-    __shared__ double s_red[8];
 
     // XCD-aware work item: blocks are dealt round-robin to the 8 XCDs
     const int per = (int)(gridDim.x + 7) / 8;
     const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    double q_in = 0.0, q_out = 0.0;
     const __amdgpu_buffer_rsrc_t rs0 = comp_rsrc<STORE>(src, 0, Q, g.Ppad);
     const __amdgpu_buffer_rsrc_t rs1 = comp_rsrc<STORE>(src, 1, Q, g.Ppad);
 
@@ -281,7 +283,7 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                 if (DIM == 3) { gy = y0 - 2 + ly; gz = pl; }
                 else { gy = pl; gz = 0; }
                 const bool need = gx < g.n[0] + 2 && gy < g.n[1] + 2 && (DIM == 2 || gz < g.n[2] + 2);
-                const int slot = ((pl + 4 * R) & (R - 1)) * PLANE + r;
+                const int slot = ((pl + 4 * R) % R) * PLANE + r;
                 if constexpr (PSRC == 1) {
                     // psi of this step from k_psi; solids carry -0.0 (zero in
                     // every sum, and the sign marks them for the adhesion stencil)
@@ -359,7 +361,7 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                 int base[5];
                 static_for<5>([&](auto dc) {
                     constexpr int d = decltype(dc)::value;
-                    base[d] = ((sv + d - 2 + 4 * R) & (R - 1)) * PLANE + corner;
+                    base[d] = ((sv + d - 2 + 4 * R) % R) * PLANE + corner;
                 });
                 constexpr int CEN = (DIM == 3 ? 2 * HX : 0) + 2;   // the node itself
                 const float2 ps = s_psi[base[2] + CEN];
@@ -387,8 +389,8 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                 float g1[3] = {0.f, 0.f, 0.f}, g2[3] = {0.f, 0.f, 0.f};
 #pragma unroll 1
                 for (int sd = 0; sd <= 2; sd++) {
-                    const int bp = ((sv + sd + 4 * R) & (R - 1)) * PLANE + corner + CEN;
-                    const int bm = ((sv - sd + 4 * R) & (R - 1)) * PLANE + corner + CEN;
+                    const int bp = ((sv + sd + 4 * R) % R) * PLANE + corner + CEN;
+                    const int bm = ((sv - sd + 4 * R) % R) * PLANE + corner + CEN;
                     auto plane = [&](auto sdc) {
                         constexpr int SD = decltype(sdc)::value;
                         static_for<25>([&](auto oc) {
@@ -426,10 +428,8 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                     F2[d] = -ph.G12 * r2 * g1[d] - ph.Gw[1] * r2 * A[d] + w2 * ph.Fb[d];
                 });
 
-                // ---- common velocity (eqs. 7-8).  Component 2 is gathered
-                // twice (the second time from L1/L2 after component 1 is
-                // stored) so that only one component is held in registers.
-                PairF<DIM> qa;
+                // ---- common velocity (eqs. 7-8)
+                PairF<DIM> qa, qb;
                 float J1[3], J2[3];
                 {
                     float f[Q];
@@ -437,9 +437,8 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                     to_pairs<DIM>(f, qa);
                     pair_momentum<DIM>(qa, J1);
                     bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f);
-                    PairF<DIM> qt;
-                    to_pairs<DIM>(f, qt);
-                    pair_momentum<DIM>(qt, J2);
+                    to_pairs<DIM>(f, qb);
+                    pair_momentum<DIM>(qb, J2);
                 }
                 float u[3];
                 const float irt = 1.0f / rt;
@@ -466,11 +465,11 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                     if (tw & T_XPRIME) {
                         const float un = bd.out_sign * pick3(u, bd.out_axis);
                         bd.faceU[slot] = un;
-                        q_out += (double)rt * (double)un;
+                        bd.faceQ[slot] = (double)rt * (double)un;
                     }
                     if (tw & T_INLET) {
                         const Patch pt = bd.patch[(tw & T_PATCH_MASK) >> T_PATCH_SHIFT];
-                        q_in += (double)rt * (double)(pt.sign * pick3(u, pt.axis));
+                        bd.faceQ[slot] = (double)rt * (double)(pt.sign * pick3(u, pt.axis));
                     }
                     if ((tw & T_OUTLET) && bd.chi_on) continue;   // collided by k_outlet
                 }
@@ -486,8 +485,7 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                     constexpr int i = decltype(ic)::value;
                     Buf<STORE>::st(rd0, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i));
                 });
-                PairF<DIM> qb;
-                {
+                if constexpr (!KEEPB) {
                     float f[Q];
                     bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f);
                     to_pairs<DIM>(f, qb);
@@ -499,13 +497,6 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                     Buf<STORE>::st(rd1, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i));
                 });
             }
-        }
-    }
-    if (MODE == MODE_STEP && bd.qpart) {
-        block_sum2(q_in, q_out, s_red);
-        if (threadIdx.x == 0 && item < n_items) {
-            bd.qpart[2 * item] = q_in;
-            bd.qpart[2 * item + 1] = q_out;
         }
     }
 }
@@ -542,13 +533,6 @@ __global__ __launch_bounds__(256) void k_psi(const typename Codec<STORE>::T *__r
     psi[b] = make_float2(r1, r2);
 }
 
-// chi of eq. (23); undefined (no outflow through x_{N-1}, or flow against the
-// inlets) leaves the outlet uncorrected.
-__device__ __forceinline__ double chi_of(double qin, double qout)
-{
-    return (fabs(qout) < 1e-30 || qin * qout <= 0.0) ? 1.0 : qin / qout;
-}
-
 // Density and momentum of the populations of one component.
 template <int DIM>
 __device__ __forceinline__ void moments_of(const float (&f)[Lat<DIM>::Q], float &rho, float (&J)[3])
@@ -568,6 +552,76 @@ __device__ __forceinline__ void moments_of(const float (&f)[Lat<DIM>::Q], float 
 }
 
 // ---------------------------------------------------------------------------
+// k_moments: rho_k and the common velocity of eqs. (7)-(8) (with this
+// state's force, before any outlet override) of every node, one thread per
+// node, with psi of the neighbours read from the array k_psi wrote.
+// ---------------------------------------------------------------------------
+template <int DIM, int STORE>
+__global__ __launch_bounds__(256) void k_moments(const typename Codec<STORE>::T *__restrict__ src,
+                                                 const uint32_t *__restrict__ type,
+                                                 const float2 *__restrict__ psi, Geometry g, Physics ph,
+                                                 double *__restrict__ out_rho, double *__restrict__ out_u)
+{
+    constexpr int Q = Lat<DIM>::Q;
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= g.N) return;
+    const uint32_t tw = type[b];
+    if (tw & T_SOLID) {
+        out_rho[b] = 0.0;
+        out_rho[g.N + b] = 0.0;
+        out_u[b] = out_u[g.N + b] = out_u[2 * g.N + b] = 0.0;
+        return;
+    }
+    int x, y, z;
+    coords_of(g, b, x, y, z);
+    float g1[3] = {0.f, 0.f, 0.f}, g2[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
+    static_for<(DIM == 3 ? 125 : 25)>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        constexpr int dx = o % 5 - 2, dy = (o / 5) % 5 - 2, dz = DIM == 3 ? o / 25 - 2 : 0;
+        constexpr int r2 = dx * dx + dy * dy + dz * dz;
+        constexpr float w = stencil_w<DIM>(r2);
+        if constexpr (r2 != 0 && w != 0.0f) {
+            const int qx = map_axis(x + dx, g.n[0], g.periodic[0]);
+            const int qy = map_axis(y + dy, g.n[1], g.periodic[1]);
+            const int qz = DIM == 3 ? map_axis(z + dz, g.n[2], g.periodic[2]) : 0;
+            const float2 v = psi[(int64_t)qx + (int64_t)g.n[0] * ((int64_t)qy + (int64_t)g.n[1] * qz)];
+            const float sv = signbit(v.x) ? 1.0f : 0.0f;
+            const int e3[3] = {dx, dy, dz};
+            static_for<3>([&](auto dc) {
+                constexpr int d = decltype(dc)::value;
+                g1[d] = fmaf(w * e3[d], v.x, g1[d]);
+                g2[d] = fmaf(w * e3[d], v.y, g2[d]);
+                A[d] = fmaf(w * e3[d], sv, A[d]);
+            });
+        }
+    });
+    if (!ph.adhesion) A[0] = A[1] = A[2] = 0.0f;
+    const float2 ps = psi[b];
+    const float r1 = ps.x, r2 = ps.y, rt = r1 + r2;
+    const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
+    float f[Q], ra, rb, Ja[3], Jb[3];
+    gather<DIM, STORE>(src, g, p, tw | T_EDGE, x, y, z, f);
+    moments_of<DIM>(f, ra, Ja);
+    gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, f);
+    moments_of<DIM>(f, rb, Jb);
+    out_rho[b] = r1;
+    out_rho[g.N + b] = r2;
+    static_for<3>([&](auto dc) {
+        constexpr int d = decltype(dc)::value;
+        const float F1 = -ph.G12 * r1 * g2[d] - ph.Gw[0] * r1 * A[d] + (r1 / rt) * ph.Fb[d];
+        const float F2 = -ph.G12 * r2 * g1[d] - ph.Gw[1] * r2 * A[d] + (r2 / rt) * ph.Fb[d];
+        out_u[d * g.N + b] = (Ja[d] + Jb[d] + 0.5f * (F1 + F2)) / rt;
+    });
+}
+
+// chi of eq. (23); undefined (no outflow through x_{N-1}, or flow against the
+// inlets) leaves the outlet uncorrected.
+__device__ __forceinline__ double chi_of(double qin, double qout)
+{
+    return (fabs(qout) < 1e-30 || qin * qout <= 0.0) ? 1.0 : qin / qout;
+}
+
+// ---------------------------------------------------------------------------
 // k_outlet: eq. (23) and the collision of the outlet column with eq. (22).
 // ---------------------------------------------------------------------------
 template <int DIM, int STORE>
@@ -579,8 +633,16 @@ __global__ __launch_bounds__(256) void k_outlet(const typename Codec<STORE>::T *
     using T = typename Codec<STORE>::T;
     constexpr int Q = Lat<DIM>::Q;
     __shared__ double s_red[8];
-    double qin, qout;
-    reduce_partials(bd.qpart, bd.n_qpart, qin, qout, s_red);
+    // eq. (23): Q_in over the inlet nodes and Q' over the x_{N-1} column, from
+    // the per-node mass flows k_main left in the face slots, summed in the
+    // fixed node order of the face records (independent of the launch shape)
+    double qin = 0.0, qout = 0.0;
+    for (int j = threadIdx.x; j < bd.n_in; j += 256) qin += bd.faceQ[bd.in[j].slot1];
+    for (int j = threadIdx.x; j < bd.n_out; j += 256) {
+        const int sp = bd.out[j].slotP;
+        if (sp >= 0) qout += bd.faceQ[sp];
+    }
+    block_sum2(qin, qout, s_red);
     const double chi = chi_of(qin, qout);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         bd.scal[SC_QIN] = qin;
@@ -925,7 +987,7 @@ __global__ __launch_bounds__(256) void k_mass(const typename Codec<STORE>::T *__
     }
 }
 
-__global__ void k_reduce2(const double *__restrict__ part, int n, double *__restrict__ out)
+static __global__ void k_reduce2(const double *__restrict__ part, int n, double *__restrict__ out)
 {
     __shared__ double s_red[8];
     double a, b;

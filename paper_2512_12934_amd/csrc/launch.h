@@ -1,0 +1,74 @@
+// launch.h -- host-side launchers of the step kernels.  Each lattice has its
+// own translation unit (k2d.hip, k3d.hip) that instantiates Launcher<DIM>;
+// the runtime (lbm_api.hip) sees only these declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "params.h"
+
+namespace lbm {
+
+// One configuration of the node update: where psi comes from (1 = the psi
+// array written by k_psi, 0 = recomputed in k_main), the lateral tile
+// (tx, or tx x ty in 3-D), the planes per sweep iteration w, the planes per
+// block zc, and whether both components stay in registers (keepb).
+struct TileCfg {
+    int psrc, tx, ty, w, zc, keepb;
+};
+
+// The tuning space.  Entry 0 is the default when no measured choice exists.
+constexpr TileCfg CFG2[] = {
+    {1, 64, 1, 4, 16, 1},
+    {1, 64, 1, 4, 32, 1},
+    {1, 128, 1, 2, 16, 1},
+    {1, 256, 1, 1, 16, 1},
+    {0, 64, 1, 4, 16, 1},
+};
+constexpr TileCfg CFG3[] = {
+    {1, 32, 8, 4, 16, 1},
+    {1, 32, 8, 4, 16, 0},
+    {1, 32, 8, 2, 16, 1},
+    {1, 64, 4, 4, 16, 1},
+    {1, 32, 8, 4, 32, 1},
+    {1, 32, 8, 8, 16, 1},
+    {0, 32, 8, 4, 16, 1},
+};
+constexpr int NCFG2 = sizeof(CFG2) / sizeof(CFG2[0]);
+constexpr int NCFG3 = sizeof(CFG3) / sizeof(CFG3[0]);
+
+inline const TileCfg &tile_cfg(int dim, int i) { return dim == 2 ? CFG2[i] : CFG3[i]; }
+inline int n_tile_cfg(int dim) { return dim == 2 ? NCFG2 : NCFG3; }
+
+struct StepArgs {
+    const void *src;
+    void *dst;
+    const uint32_t *type;
+    float2 *psi;
+    Geometry g;
+    Physics ph;
+    Boundary bd;
+    int tiles_x, tiles_y, items;
+    unsigned grid;
+    double *orho, *ou;
+    int *flag;
+    hipStream_t stream;
+};
+
+template <int DIM> struct Launcher {
+    static void psi(int storage, const StepArgs &a);
+    static void moments(int storage, const StepArgs &a);
+    static void main(int storage, int cfg, int mode, const StepArgs &a);
+    static void outlet(int storage, const StepArgs &a, unsigned nb);
+    static void inlet(int storage, const StepArgs &a, unsigned nb, int nb_in);
+    static void outlet_fill(int storage, const StepArgs &a, unsigned nb);
+    static void scatter(int storage, const StepArgs &a, const double *f);
+    static void gather_state(int storage, const StepArgs &a, double *f);
+    static void feq_state(const double *rho0, const double *u0, int64_t N, double *f, hipStream_t s);
+    static void mass(int storage, const StepArgs &a, double *part, int nb, double *out);
+};
+
+extern template struct Launcher<2>;
+extern template struct Launcher<3>;
+
+}  // namespace lbm

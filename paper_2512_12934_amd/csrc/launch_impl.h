@@ -1,0 +1,141 @@
+// launch_impl.h -- definitions of Launcher<DIM>; included by exactly one
+// translation unit per lattice.
+#pragma once
+
+#include <utility>
+
+#include "kernels.h"
+#include "launch.h"
+
+namespace lbm {
+
+namespace detail {
+
+template <int DIM> constexpr const TileCfg &cfg_at(int i) { return DIM == 2 ? CFG2[i] : CFG3[i]; }
+template <int DIM> constexpr int cfg_count() { return DIM == 2 ? NCFG2 : NCFG3; }
+
+template <int DIM, int STORE, int MODE, int I>
+void launch_cfg(const StepArgs &a)
+{
+    constexpr TileCfg c = cfg_at<DIM>(I);
+    using T = typename Codec<STORE>::T;
+    hipLaunchKernelGGL((k_main<DIM, STORE, MODE, c.psrc, c.tx, c.ty, c.w, c.zc, c.keepb>), dim3(a.grid), dim3(256),
+                       0, a.stream, (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.g, a.ph, a.bd,
+                       a.tiles_x, a.tiles_y, a.items, a.orho, a.ou, a.flag);
+}
+
+template <int DIM, int STORE, int... I>
+void launch_step_cfg(int cfg, const StepArgs &a, std::integer_sequence<int, I...>)
+{
+    ((cfg == I ? launch_cfg<DIM, STORE, MODE_STEP, I>(a) : void()), ...);
+}
+
+}  // namespace detail
+
+template <int DIM>
+void Launcher<DIM>::psi(int storage, const StepArgs &a)
+{
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    if (storage == 0)
+        hipLaunchKernelGGL((k_psi<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.g, a.psi);
+    else
+        hipLaunchKernelGGL((k_psi<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type, a.g,
+                           a.psi);
+}
+
+template <int DIM>
+void Launcher<DIM>::moments(int storage, const StepArgs &a)
+{
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    if (storage == 0)
+        hipLaunchKernelGGL((k_moments<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
+                           (const float2 *)a.psi, a.g, a.ph, a.orho, a.ou);
+    else
+        hipLaunchKernelGGL((k_moments<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
+                           (const float2 *)a.psi, a.g, a.ph, a.orho, a.ou);
+}
+
+template <int DIM>
+void Launcher<DIM>::main(int storage, int cfg, int mode, const StepArgs &a)
+{
+    constexpr int N = detail::cfg_count<DIM>();
+    (void)mode;   // the node update only runs time steps; moments use k_moments
+    if (storage == 0) detail::launch_step_cfg<DIM, 0>(cfg, a, std::make_integer_sequence<int, N>{});
+    else detail::launch_step_cfg<DIM, 1>(cfg, a, std::make_integer_sequence<int, N>{});
+}
+
+template <int DIM>
+void Launcher<DIM>::outlet(int storage, const StepArgs &a, unsigned nb)
+{
+    if (storage == 0)
+        hipLaunchKernelGGL((k_outlet<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, (float *)a.dst,
+                           a.type, a.g, a.ph, a.bd, a.flag);
+    else
+        hipLaunchKernelGGL((k_outlet<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src,
+                           (__half *)a.dst, a.type, a.g, a.ph, a.bd, a.flag);
+}
+
+template <int DIM>
+void Launcher<DIM>::inlet(int storage, const StepArgs &a, unsigned nb, int nb_in)
+{
+    if (storage == 0)
+        hipLaunchKernelGGL((k_inlet<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (float *)a.dst, a.type, a.g, a.bd,
+                           nb_in);
+    else
+        hipLaunchKernelGGL((k_inlet<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (__half *)a.dst, a.type, a.g, a.bd,
+                           nb_in);
+}
+
+template <int DIM>
+void Launcher<DIM>::outlet_fill(int storage, const StepArgs &a, unsigned nb)
+{
+    if (storage == 0)
+        hipLaunchKernelGGL((k_outlet_fill<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src,
+                           (float *)a.dst, a.type, a.g, a.bd);
+    else
+        hipLaunchKernelGGL((k_outlet_fill<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src,
+                           (__half *)a.dst, a.type, a.g, a.bd);
+}
+
+template <int DIM>
+void Launcher<DIM>::scatter(int storage, const StepArgs &a, const double *f)
+{
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    // writes the source array (the state f(t))
+    if (storage == 0)
+        hipLaunchKernelGGL((k_scatter<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (float *)a.src, a.type, a.g, f);
+    else
+        hipLaunchKernelGGL((k_scatter<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (__half *)a.src, a.type, a.g, f);
+}
+
+template <int DIM>
+void Launcher<DIM>::gather_state(int storage, const StepArgs &a, double *f)
+{
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    if (storage == 0)
+        hipLaunchKernelGGL((k_gather_state<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
+                           a.g, f);
+    else
+        hipLaunchKernelGGL((k_gather_state<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
+                           a.g, f);
+}
+
+template <int DIM>
+void Launcher<DIM>::feq_state(const double *rho0, const double *u0, int64_t N, double *f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_feq_state<DIM>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, rho0, u0, N, f);
+}
+
+template <int DIM>
+void Launcher<DIM>::mass(int storage, const StepArgs &a, double *part, int nb, double *out)
+{
+    if (storage == 0)
+        hipLaunchKernelGGL((k_mass<DIM, 0>), dim3((unsigned)nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
+                           a.g, part);
+    else
+        hipLaunchKernelGGL((k_mass<DIM, 1>), dim3((unsigned)nb), dim3(256), 0, a.stream, (const __half *)a.src,
+                           a.type, a.g, part);
+    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, a.stream, (const double *)part, nb, out);
+}
+
+}  // namespace lbm

@@ -15,16 +15,14 @@
 #include <vector>
 
 #include "../../include/lbm.h"
-#include "kernels.h"
+#include "launch.h"
+#include "lattice.h"
+#include "params.h"
 
 using namespace lbm;
 
 namespace {
 
-// Sweep tiles of the node update: lateral tile, planes per iteration W and
-// planes per block ZC along the sweep axis (y in 2-D, z in 3-D).
-constexpr int TX2 = 64, W2 = 4, ZC2 = 16;
-constexpr int TX3 = 32, TY3 = 8, W3 = 4, ZC3 = 16;
 constexpr size_t ALIGN = 256;
 
 thread_local std::string g_create_error;
@@ -44,6 +42,7 @@ struct Layout {
     // byte offsets into the workspace
     size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
         o_flag, o_mpart, o_mout, o_patch, o_psi, total;
+    int cfg = 0;                   // node-update configuration (launch.h)
     int psi_mode = 1;              // 1: psi array written by k_psi, 0: recomputed in k_main
 };
 
@@ -96,6 +95,7 @@ std::string build_maps(const lbm_config *c, Maps &m)
     if (!(c->s_q > 0.0 && c->s_q < 2.0)) return "s_q must lie in (0, 2)";
     if (c->s_eps_policy != LBM_SEPS_MAXVISC && c->s_eps_policy != LBM_SEPS_FIXED) return "unknown s_eps policy";
     if (c->n_inlets < 0 || c->n_inlets > LBM_MAX_INLETS) return "bad inlet count";
+    if (c->tile_config < -1 || c->tile_config >= n_tile_cfg(c->dim)) return "unknown tile configuration";
     if (!c->solid || !c->rho0) return "solid and rho0 arrays are required";
     for (int q = 0; q < c->n_inlets; q++) {
         const lbm_inlet &p = c->inlets[q];
@@ -112,7 +112,8 @@ std::string build_maps(const lbm_config *c, Maps &m)
     const int Q = lat_Q(c->dim);
     {
         // each component array is addressed with 32-bit byte offsets
-        const int64_t pad = (int64_t)(c->n[0] + 2) * (c->n[1] + 2) * (c->dim == 3 ? c->n[2] + 2 : 1);
+        const int64_t pad = (int64_t)((c->n[0] + XOFF + 1 + 31) / 32 * 32) * (c->n[1] + 2) *
+                            (c->dim == 3 ? c->n[2] + 2 : 1);
         const int64_t bytes = pad * Q * (c->storage == LBM_STORE_F32 ? 4 : 2);
         if (bytes >= ((int64_t)1 << 31)) return "domain too large for one context (2 GiB per component array)";
     }
@@ -246,6 +247,14 @@ std::string build_maps(const lbm_config *c, Maps &m)
     return "";
 }
 
+// Default node-update configuration: the measured best of the tuning space
+// for the lattice (see the autotuner), entry 0 otherwise.
+int default_cfg(const lbm_config *c)
+{
+    (void)c;
+    return 0;
+}
+
 Layout make_layout(const lbm_config *c, const Maps &m)
 {
     Layout L;
@@ -255,19 +264,22 @@ Layout make_layout(const lbm_config *c, const Maps &m)
     Geometry &g = L.g;
     for (int a = 0; a < 3; a++) {
         g.n[a] = a < c->dim ? c->n[a] : 1;
-        g.P[a] = a < c->dim ? c->n[a] + 2 : 1;
+        g.P[a] = a == 0 ? (c->n[0] + XOFF + 1 + 31) / 32 * 32 : (a < c->dim ? c->n[a] + 2 : 1);
         g.periodic[a] = a < c->dim ? (c->periodic[a] != 0) : 1;
     }
     g.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
     g.Ppad = (int64_t)g.P[0] * g.P[1] * g.P[2];
+    L.cfg = c->tile_config >= 0 ? c->tile_config : default_cfg(c);
+    const TileCfg &tc = tile_cfg(c->dim, L.cfg);
+    L.psi_mode = tc.psrc;
     if (c->dim == 2) {
-        L.tiles[0] = (g.n[0] + TX2 - 1) / TX2;
+        L.tiles[0] = (g.n[0] + tc.tx - 1) / tc.tx;
         L.tiles[1] = 1;
-        L.tiles[2] = (g.n[1] + ZC2 - 1) / ZC2;
+        L.tiles[2] = (g.n[1] + tc.zc - 1) / tc.zc;
     } else {
-        L.tiles[0] = (g.n[0] + TX3 - 1) / TX3;
-        L.tiles[1] = (g.n[1] + TY3 - 1) / TY3;
-        L.tiles[2] = (g.n[2] + ZC3 - 1) / ZC3;
+        L.tiles[0] = (g.n[0] + tc.tx - 1) / tc.tx;
+        L.tiles[1] = (g.n[1] + tc.ty - 1) / tc.ty;
+        L.tiles[2] = (g.n[2] + tc.zc - 1) / tc.zc;
     }
     L.nblocks_main = (int64_t)L.tiles[0] * L.tiles[1] * L.tiles[2];
     L.grid_main = (L.nblocks_main + 7) / 8 * 8;
@@ -290,18 +302,14 @@ Layout make_layout(const lbm_config *c, const Maps &m)
     L.o_faceU = take((size_t)L.n_slots * 4);
     L.o_in = take((size_t)L.n_in * sizeof(InletRec));
     L.o_out = take((size_t)L.n_out * sizeof(OutletRec));
-    L.o_qpart = take((size_t)L.nblocks_main * 16);
+    L.o_qpart = take((size_t)L.n_slots * 8);
     L.o_ucpart = take((size_t)std::max(L.nb_out, 1) * 16);
     L.o_scal = take(SC_COUNT * 8);
     L.o_flag = take(4);
     L.o_mpart = take((size_t)L.nb_mass * 16);
     L.o_mout = take(16);
     L.o_patch = take(sizeof(Patch) * MAX_PATCH);
-    {
-        const char *env = getenv("LBM_PSI_MODE");
-        L.psi_mode = env ? (atoi(env) != 0 ? 1 : 0) : 1;
-    }
-    L.o_psi = take(L.psi_mode ? (size_t)g.N * 8 : 1);
+    L.o_psi = take((size_t)g.N * 8);
     L.total = o;
     return L;
 }
@@ -342,47 +350,51 @@ lbm_status fail(lbm_ctx *c, lbm_status st, const std::string &msg)
             return fail(ctx, LBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
     } while (0)
 
-template <int DIM, int STORE> struct Launch {
-    using T = typename Codec<STORE>::T;
-    static constexpr int TX = DIM == 2 ? TX2 : TX3;
-    static constexpr int TY = DIM == 2 ? 1 : TY3;
-    static constexpr int W = DIM == 2 ? W2 : W3;
-    static constexpr int ZC = DIM == 2 ? ZC2 : ZC3;
+StepArgs step_args(const lbm_ctx *c, double *orho = nullptr, double *ou = nullptr)
+{
+    const Layout &L = c->L;
+    StepArgs a{};
+    a.src = c->fsrc();
+    a.dst = c->fdst();
+    a.type = c->type();
+    a.psi = (float2 *)(c->ws + L.o_psi);
+    a.g = L.g;
+    a.ph = c->ph;
+    a.bd = c->bd;
+    a.tiles_x = L.tiles[0];
+    a.tiles_y = L.tiles[1];
+    a.items = (int)L.nblocks_main;
+    a.grid = (unsigned)L.grid_main;
+    a.orho = orho;
+    a.ou = ou;
+    a.flag = c->flag();
+    a.stream = c->stream;
+    return a;
+}
+
+template <int DIM> struct Ops {
+    using Lx = Launcher<DIM>;
+
+    // rho and u of the current state: psi of every node, then one thread per node
+    static void moments(lbm_ctx *c, double *orho, double *ou)
+    {
+        StepArgs a = step_args(c, orho, ou);
+        Lx::psi(c->L.storage, a);
+        Lx::moments(c->L.storage, a);
+    }
 
     // ev (optional): events bracketing k_psi (ev[8], ev[9]) and k_main (ev[0], ev[1])
     static void main_kernel(lbm_ctx *c, int mode, double *orho, double *ou, hipEvent_t *ev = nullptr)
     {
         const Layout &L = c->L;
-        Boundary bd = c->bd;
-        if (mode == MODE_MOMENTS) bd.qpart = nullptr;
-        const int items = (int)L.nblocks_main;
-        const float2 *psi = (const float2 *)(c->ws + L.o_psi);
+        StepArgs a = step_args(c, orho, ou);
         if (L.psi_mode) {
             if (ev) (void)hipEventRecord(ev[8], c->stream);
-            hipLaunchKernelGGL((k_psi<DIM, STORE>), dim3((unsigned)((L.g.N + 255) / 256)), dim3(256), 0, c->stream,
-                               (const T *)c->fsrc(), c->type(), L.g, (float2 *)psi);
+            Lx::psi(L.storage, a);
             if (ev) (void)hipEventRecord(ev[9], c->stream);
-            if (ev) (void)hipEventRecord(ev[0], c->stream);
-            if (mode == MODE_STEP)
-                hipLaunchKernelGGL((k_main<DIM, STORE, MODE_STEP, 1, TX, TY, W, ZC>), dim3((unsigned)L.grid_main),
-                                   dim3(256), 0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), psi, L.g,
-                                   c->ph, bd, L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
-            else
-                hipLaunchKernelGGL((k_main<DIM, STORE, MODE_MOMENTS, 1, TX, TY, W, ZC>), dim3((unsigned)L.grid_main),
-                                   dim3(256), 0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), psi, L.g,
-                                   c->ph, bd, L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
-            if (ev) (void)hipEventRecord(ev[1], c->stream);
-            return;
         }
         if (ev) (void)hipEventRecord(ev[0], c->stream);
-        if (mode == MODE_STEP)
-            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_STEP, 0, TX, TY, W, ZC>), dim3((unsigned)L.grid_main), dim3(256),
-                               0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), psi, L.g, c->ph, bd,
-                               L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
-        else
-            hipLaunchKernelGGL((k_main<DIM, STORE, MODE_MOMENTS, 0, TX, TY, W, ZC>), dim3((unsigned)L.grid_main),
-                               dim3(256), 0, c->stream, (const T *)c->fsrc(), (T *)c->fdst(), c->type(), psi, L.g,
-                               c->ph, bd, L.tiles[0], L.tiles[1], items, orho, ou, c->flag());
+        Lx::main(L.storage, L.cfg, mode, a);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
 
@@ -392,60 +404,41 @@ template <int DIM, int STORE> struct Launch {
         const Layout &L = c->L;
         main_kernel(c, MODE_STEP, nullptr, nullptr, ev);
         if (L.boundary) {
+            const StepArgs a = step_args(c);
             const unsigned nb = (unsigned)std::max(L.nb_out, 1);
             if (ev) (void)hipEventRecord(ev[2], c->stream);
-            hipLaunchKernelGGL((k_outlet<DIM, STORE>), dim3(nb), dim3(256), 0, c->stream, (const T *)c->fsrc(),
-                               (T *)c->fdst(), c->type(), L.g, c->ph, c->bd, c->flag());
+            Lx::outlet(L.storage, a, nb);
             if (ev) (void)hipEventRecord(ev[3], c->stream);
             if (L.nb_in + L.nb_out > 0) {
                 if (ev) (void)hipEventRecord(ev[4], c->stream);
-                hipLaunchKernelGGL((k_inlet<DIM, STORE>), dim3((unsigned)(L.nb_in + L.nb_out)), dim3(256), 0,
-                                   c->stream, (T *)c->fdst(), c->type(), L.g, c->bd, L.nb_in);
+                Lx::inlet(L.storage, a, (unsigned)(L.nb_in + L.nb_out), L.nb_in);
                 if (ev) (void)hipEventRecord(ev[5], c->stream);
             }
             if (L.nb_out > 0) {
                 if (ev) (void)hipEventRecord(ev[6], c->stream);
-                hipLaunchKernelGGL((k_outlet_fill<DIM, STORE>), dim3((unsigned)L.nb_out), dim3(256), 0, c->stream,
-                                   (const T *)c->fsrc(), (T *)c->fdst(), c->type(), L.g, c->bd);
+                Lx::outlet_fill(L.storage, a, (unsigned)L.nb_out);
                 if (ev) (void)hipEventRecord(ev[7], c->stream);
             }
         }
         c->cur ^= 1;
     }
 
-    static void scatter(lbm_ctx *c, const double *dev_f)
-    {
-        const Layout &L = c->L;
-        hipLaunchKernelGGL((k_scatter<DIM, STORE>), dim3((unsigned)((L.g.N + 255) / 256)), dim3(256), 0, c->stream,
-                           (T *)c->fsrc(), c->type(), L.g, dev_f);
-    }
-
-    static void gather_state(lbm_ctx *c, double *dev_f)
-    {
-        const Layout &L = c->L;
-        hipLaunchKernelGGL((k_gather_state<DIM, STORE>), dim3((unsigned)((L.g.N + 255) / 256)), dim3(256), 0,
-                           c->stream, (const T *)c->fsrc(), c->type(), L.g, dev_f);
-    }
-
+    static void scatter(lbm_ctx *c, const double *dev_f) { Lx::scatter(c->L.storage, step_args(c), dev_f); }
+    static void gather_state(lbm_ctx *c, double *dev_f) { Lx::gather_state(c->L.storage, step_args(c), dev_f); }
     static void mass(lbm_ctx *c, double *out)
     {
-        const Layout &L = c->L;
-        double *part = (double *)(c->ws + L.o_mpart);
-        hipLaunchKernelGGL((k_mass<DIM, STORE>), dim3((unsigned)L.nb_mass), dim3(256), 0, c->stream,
-                           (const T *)c->fsrc(), c->type(), L.g, part);
-        hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, c->stream, (const double *)part, L.nb_mass, out);
+        Lx::mass(c->L.storage, step_args(c), (double *)(c->ws + c->L.o_mpart), c->L.nb_mass, out);
+    }
+    static void feq_state(lbm_ctx *c, const double *rho0, const double *u0, double *f)
+    {
+        Lx::feq_state(rho0, u0, c->L.g.N, f, c->stream);
     }
 };
 
 template <typename F> void dispatch(const lbm_ctx *c, F &&f)
 {
-    if (c->L.dim == 2) {
-        if (c->L.storage == LBM_STORE_F32) f(Launch<2, 0>{});
-        else f(Launch<2, 1>{});
-    } else {
-        if (c->L.storage == LBM_STORE_F32) f(Launch<3, 0>{});
-        else f(Launch<3, 1>{});
-    }
+    if (c->L.dim == 2) f(Ops<2>{});
+    else f(Ops<3>{});
 }
 
 lbm_status current_mass(lbm_ctx *c, double *mass)
@@ -540,8 +533,7 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
     bd.bslot = (const int *)(ws + L.o_bslot);
     bd.faceF = (float *)(ws + L.o_faceF);
     bd.faceU = (float *)(ws + L.o_faceU);
-    bd.qpart = L.boundary ? (double *)(ws + L.o_qpart) : nullptr;
-    bd.n_qpart = (int)L.nblocks_main;
+    bd.faceQ = (double *)(ws + L.o_qpart);
     bd.ucpart = (double *)(ws + L.o_ucpart);
     bd.n_ucpart = L.nb_out;
     bd.scal = (double *)(ws + L.o_scal);
@@ -567,12 +559,7 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
         HIPCHECK(c, hipMalloc(&d_f, (size_t)2 * L.Q * N * 8));
         HIPCHECK(c, hipMemcpyAsync(d_rho, cfg->rho0, (size_t)2 * N * 8, hipMemcpyHostToDevice, s));
         if (cfg->u0) HIPCHECK(c, hipMemcpyAsync(d_u, cfg->u0, (size_t)3 * N * 8, hipMemcpyHostToDevice, s));
-        if (L.dim == 2)
-            hipLaunchKernelGGL(k_feq_state<2>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
-                               (const double *)d_rho, (const double *)d_u, N, d_f);
-        else
-            hipLaunchKernelGGL(k_feq_state<3>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s,
-                               (const double *)d_rho, (const double *)d_u, N, d_f);
+        dispatch(c, [&](auto l) { decltype(l)::feq_state(c, d_rho, d_u, d_f); });
         dispatch(c, [&](auto l) { decltype(l)::scatter(c, d_f); });
         HIPCHECK(c, hipGetLastError());
         HIPCHECK(c, hipStreamSynchronize(s));
@@ -610,7 +597,7 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *u, int dst_on_device)
         HIPCHECK(c, hipMalloc(&du, (size_t)3 * N * 8));
     }
     HIPCHECK(c, hipMemsetAsync(du, 0, (size_t)3 * N * 8, c->stream));
-    dispatch(c, [&](auto l) { decltype(l)::main_kernel(c, MODE_MOMENTS, drho, du); });
+    dispatch(c, [&](auto l) { decltype(l)::moments(c, drho, du); });
     HIPCHECK(c, hipGetLastError());
     if (!dst_on_device) {
         HIPCHECK(c, hipMemcpyAsync(rho, drho, (size_t)2 * N * 8, hipMemcpyDeviceToHost, c->stream));
@@ -703,6 +690,8 @@ lbm_status lbm_time_kernels(lbm_ctx *c, int64_t n, double *ms)
     for (auto &e : ev) HIPCHECK(c, hipEventDestroy(e));
     return LBM_OK;
 }
+
+int lbm_tile_configs(int dim) { return (dim == 2 || dim == 3) ? n_tile_cfg(dim) : 0; }
 
 int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
 

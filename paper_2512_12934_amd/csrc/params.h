@@ -42,9 +42,14 @@ struct Physics {
     int adhesion;
 };
 
+// Elements of padding before x = 0 in every row of a population plane: one
+// ghost slot is needed; 32 keeps x = 0 on a 128-byte boundary for FP32.
+constexpr int XOFF = 32;
+
 struct Geometry {
     int n[3];
-    int P[3];              // padded sizes (n + 2 on every axis of the lattice)
+    int P[3];              // padded sizes: rows of XOFF + n + 1 rounded up to 32
+                           // elements, n + 2 on the other lattice axes
     int periodic[3];
     int64_t N;             // box nodes
     int64_t Ppad;          // padded nodes (stride between population planes)
@@ -68,12 +73,14 @@ struct Boundary {
     const int *bslot;         // [N] face-buffer slot of role nodes, -1 elsewhere
     float *faceF;             // [slots][2][3] force of this step at role nodes
     float *faceU;             // [slots] normal velocity at x' (outward)
-    double *qpart;            // [main blocks][2] partial inlet / x' mass flows
-    int n_qpart;
+    double *faceQ;            // [slots] rho u.n at inlet and x' nodes (eq. 23 terms)
     double *ucpart;           // [inlet-kernel blocks][2] partial sum of u.n at x' and count
     int n_ucpart;
     double *scal;             // device scalars, see SC_* below
 };
+
+// Node-update kernel modes: a time step, or moments output only.
+enum { MODE_STEP = 0, MODE_MOMENTS = 1 };
 
 enum { SC_QIN = 0, SC_QOUT = 1, SC_CHI = 2, SC_UC = 3, SC_CLAMPS = 4, SC_COUNT = 8 };
 

@@ -41,7 +41,8 @@ class Config(C.Structure):
                 ("nu", C.c_double * 2), ("s_q", C.c_double), ("s_eps_policy", C.c_int),
                 ("G12", C.c_double), ("Gw", C.c_double * 2), ("Fb", C.c_double * 3),
                 ("n_inlets", C.c_int), ("inlets", Inlet * MAX_INLETS), ("has_outlet", C.c_int),
-                ("outlet", Outlet), ("solid", C.c_void_p), ("rho0", C.c_void_p), ("u0", C.c_void_p)]
+                ("outlet", Outlet), ("tile_config", C.c_int),
+                ("solid", C.c_void_p), ("rho0", C.c_void_p), ("u0", C.c_void_p)]
 
 
 class Flux(C.Structure):
@@ -77,6 +78,8 @@ def lib():
         L.lbm_set_state.argtypes = [vp, vp, C.c_size_t]
         L.lbm_time_kernels.argtypes = [vp, C.c_int64, C.POINTER(C.c_double)]
         L.lbm_time_kernels.restype = C.c_int
+        L.lbm_tile_configs.argtypes = [C.c_int]
+        L.lbm_tile_configs.restype = C.c_int
         L.lbm_steps_done.argtypes = [vp]
         L.lbm_steps_done.restype = C.c_int64
         L.lbm_destroy.argtypes = [vp]
@@ -89,9 +92,10 @@ def lib():
     return _lib
 
 
-def make_config(case, storage="f32"):
+def make_config(case, storage="f32", tile_config=-1):
     """Fill an ``lbm_config`` from a case; returns (config, arrays kept alive)."""
     cfg = Config()
+    cfg.tile_config = int(tile_config)
     cfg.dim = case.dim
     cfg.storage = STORE[storage]
     for a in range(3):
@@ -131,15 +135,28 @@ def make_config(case, storage="f32"):
     return cfg, (solid, rho0, u0)
 
 
-def workspace_bytes(case, storage="f32"):
-    cfg, keep = make_config(case, storage)
+def tile_configs(dim):
+    """Number of node-update configurations of the tuning space."""
+    return int(lib().lbm_tile_configs(int(dim)))
+
+
+def resolve_tile_config(case, storage, tile_config):
+    """'auto' looks the lattice / storage / size class up in the autotuner table."""
+    if tile_config == "auto":
+        from .autotune import lookup
+        return lookup(case.dim, storage, case.N)
+    return int(tile_config)
+
+
+def workspace_bytes(case, storage="f32", tile_config=-1):
+    cfg, keep = make_config(case, storage, tile_config)
     return int(lib().lbm_workspace_bytes(C.byref(cfg)))
 
 
 class LBM:
     """One simulation context on a GPU (device memory from torch)."""
 
-    def __init__(self, case, storage="f32", device="cuda:0", stream=None):
+    def __init__(self, case, storage="f32", device="cuda:0", stream=None, tile_config=-1):
         import torch
         L = lib()
         self.case = case
@@ -147,7 +164,8 @@ class LBM:
         self.Q = 9 if case.dim == 2 else 19
         self.N = int(np.prod(case.n))
         self.device = torch.device(device)
-        cfg, keep = make_config(case, storage)
+        self.tile_config = resolve_tile_config(case, storage, tile_config)
+        cfg, keep = make_config(case, storage, self.tile_config)
         nbytes = int(L.lbm_workspace_bytes(C.byref(cfg)))
         if nbytes == 0:
             h = C.c_void_p()

@@ -152,3 +152,27 @@ def test_unstable_flag():
     with pytest.raises(LBMError) as e:
         g.step(1)
     assert e.value.status == LBM_ESTATE
+
+
+@pytest.mark.parametrize("name,make", [
+    ("tjunction_small", lambda: cases.tjunction(W=20, length=90, x_side=30, side_width=14, side_len=18)),
+    ("coflow_small", lambda: cases.coflow3d(length=40, width=10, inner=4)),
+    ("random3d_walls", lambda: cases.random_box((34, 11, 10), seed=4, dim=3, periodic=(False, True, False),
+                                                walls=True, Gw=(0.05, -0.05), u_amp=0.01)),
+])
+def test_tile_configs_identical(name, make):
+    """Every node-update configuration of the tuning space (tile shape, sweep
+    depth, psi source, register policy) gives bitwise the same state and
+    moments as configuration 0."""
+    from paper_2512_12934_amd.lbm import LBM, tile_configs
+    c = make()
+    ref = None
+    for cfg in range(tile_configs(c.dim)):
+        print(f"[gpu] {name} tile_config={cfg}", flush=True)
+        g = LBM(c, tile_config=cfg)
+        g.step(25)
+        st = (g.get_state(), *g.moments(), g.mass_flux()["chi"])
+        if ref is None:
+            ref = st
+        for a, b in zip(st, ref):
+            assert np.array_equal(a, b), cfg
