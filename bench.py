@@ -68,7 +68,7 @@ def main():
     case = cases.coflow3d(length=args.length, width=args.width, inner=args.inner)
     fluid = case.fluid_nodes
     print(f"[bench] building {case.name} box {case.n} fluid {fluid}", file=sys.stderr, flush=True)
-    sim = LBM(case, storage=args.storage, device=dev)
+    sim = LBM(case, storage=args.storage, device=dev, tile_config="auto")
     stream = sim.stream
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -100,7 +100,8 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "k_main<3,%d>" % (0 if args.storage == "f32" else 1),
             "kernel_ms": round(kms[0], 5), "bytes_per_node": b_main, "nodes_per_launch": fluid,
-            "mode": "two-pass (k_psi + k_main)" if two_pass else "fused (k_main only)"}
+            "mode": "two-pass (k_psi + k_main)" if two_pass else "fused (k_main only)",
+            "tile_config": sim.tile_config}
     del sim
     torch.cuda.empty_cache()
 
@@ -108,7 +109,7 @@ def main():
     if not args.no_extra:
         # FP16-offset storage of the same workload, and the 2-D T-junction
         other = "f16" if args.storage == "f32" else "f32"
-        s2 = LBM(case, storage=other, device=dev)
+        s2 = LBM(case, storage=other, device=dev, tile_config="auto")
         s2.step(10)
         torch.cuda.synchronize()
         t0.record(s2.stream)
@@ -119,7 +120,7 @@ def main():
         extra[f"{other}_storage"] = {"ms_per_step": round(m2, 4), "MLUPS": round(fluid / (m2 / 1e3) / 1e6, 1)}
         del s2
         tj = cases.tjunction()
-        s3 = LBM(tj, storage="f32", device=dev)
+        s3 = LBM(tj, storage="f32", device=dev, tile_config="auto")
         s3.step(50)
         torch.cuda.synchronize()
         n3 = 2000

@@ -73,6 +73,8 @@ typedef struct {
 
 /* Problem description.  Every array is host memory owned by the caller and
  * copied by lbm_create. */
+enum { LBM_LAYOUT_CALLER = 0, LBM_LAYOUT_FACE_LAST = 1 };
+
 typedef struct {
     int dim;                 /* 2: D2Q9, 3: D3Q19 */
     int storage;             /* LBM_STORE_F32 or LBM_STORE_F16_OFFSET (f - w_i in binary16) */
@@ -91,6 +93,12 @@ typedef struct {
     int tile_config;         /* node-update configuration, -1 = library default
                                 (an index into the tuning space; the autotuner
                                 measures them) */
+    int layout;              /* LBM_LAYOUT_CALLER: memory axes are the caller's;
+                                LBM_LAYOUT_FACE_LAST (3-D): the axis normal to the
+                                open faces is stored last, so face nodes are
+                                contiguous (faster face kernels, slower node
+                                update on the 600x120x120 device).  Outputs are
+                                in the caller's frame either way. */
     const uint8_t *solid;    /* [N], 1 = solid; every fluid node on a
                                 non-periodic face must belong to a patch */
     const double *rho0;      /* [2][N] initial component densities (> 0 on fluid) */
@@ -125,8 +133,17 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes,
 
 /* Enqueues n >= 0 time steps on the context stream and returns without
  * waiting.  Errors raised on the device surface at the next synchronising
- * call.  LBM_ESTATE if the context was already flagged unstable. */
+ * call.  LBM_ESTATE if the context was already flagged unstable.  Whole
+ * groups of lbm_set_graph_steps() steps are replayed from a HIP graph
+ * (captured on a private stream the first time, launched on the context
+ * stream); the remainder, and every step enqueued while the context stream is
+ * itself being captured by the caller, are launched one kernel at a time.
+ * Both routes run the same kernels on the same data. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Steps per replayed graph (0 = never use graphs; default 16; at most 4096).
+ * Drops graphs captured so far.  LBM_EINVAL for a value out of range. */
+lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int steps_per_graph);
 
 /* Synchronises the stream and writes rho [2][N] and the common velocity
  * u [3][N] of eqs. (7)-(8) (half-force included, before any outlet
@@ -148,7 +165,7 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *f_host, size_t bytes);
 /* Measurement hook: enqueues n steps like lbm_step, bracketing every kernel
  * launch with HIP events on the context stream, then synchronises and writes
  * the mean duration in milliseconds of each launch kind into ms[5]:
- * [0] the node update, [1] the outlet collision, [2] the inlet
+ * [0] the node update, [1] the eq. (23) sums and the outlet collision, [2] the inlet
  * reconstruction, [3] the outlet fill, [4] the density pass that precedes
  * the node update in the two-pass mode (0 where a kind is not launched). */
 lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *ms);
@@ -166,6 +183,140 @@ void lbm_destroy(lbm_ctx *ctx);
 
 /* Last error message of ctx (or of the last failed lbm_create if ctx is NULL). */
 const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent contexts advanced together, one launch per stage
+ * of the step for all members (the node update as one persistent launch over
+ * the members' concatenated work items), with the step loop replayed from a
+ * HIP graph.  Members share dim and storage; the node-update configuration
+ * is cfgs[0].tile_config for every member.  They differ in everything else
+ * (size, geometry, viscosities, forces, faces).  Each member computes exactly
+ * what its own context would compute with lbm_step (same kernels, same
+ * arithmetic, bitwise identical results).
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+/* Device workspace bytes for the n members cfgs[0..n); 0 if any is invalid
+ * or the members do not share dim and storage. */
+size_t lbm_batch_workspace_bytes(const lbm_config *cfgs, int n);
+
+/* Creates every member (as lbm_create would, inside the one caller-owned
+ * workspace: 256-byte aligned, ws_bytes long, outliving the batch) and the
+ * device tables of the batched launches.  Same status codes as lbm_create;
+ * the message names the failing member. */
+lbm_status lbm_batch_create(const lbm_config *cfgs, int n, void *dev_ws, size_t ws_bytes,
+                            void *hip_stream, lbm_batch **out);
+
+/* Enqueues n steps of every member on the batch stream without waiting.
+ * LBM_ESTATE if a member is flagged unstable or was stepped on its own since
+ * the last batch step (its A/B parity differs from the batch's). */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
+
+/* Steps per replayed graph for lbm_batch_step (0 = plain launches; default 16). */
+lbm_status lbm_batch_set_graph_steps(lbm_batch *b, int steps_per_graph);
+
+/* Number of members; 0 for NULL. */
+int lbm_batch_size(const lbm_batch *b);
+
+/* Member i as a context, for lbm_moments, lbm_mass_flux, lbm_get_state and
+ * lbm_set_state (owned by the batch: do not destroy it).  NULL if i is out of
+ * range. */
+lbm_ctx *lbm_batch_member(lbm_batch *b, int i);
+
+/* Releases the batch and its members (not the workspace).  NULL is ignored. */
+void lbm_batch_destroy(lbm_batch *b);
+
+/* Last error of b (or of the last failed lbm_batch_create if b is NULL). */
+const char *lbm_batch_last_error(const lbm_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Droplet labels (droplet size and generation period, Sec. III D).  The
+ * dispersed phase is the set of fluid nodes inside a box whose component-k
+ * density, summed from the current populations in FP32, exceeds threshold.
+ * ------------------------------------------------------------------------ */
+
+/* An axis-aligned box of nodes [lo, hi) in the caller's frame (2-D: lo[2] = 0,
+ * hi[2] = 1). */
+typedef struct {
+    int lo[3], hi[3];
+} lbm_box;
+
+/* One face-connected component (4-neighbour in 2-D, 6-neighbour in 3-D). */
+typedef struct {
+    int64_t first;   /* smallest node index (x fastest) of the component */
+    int64_t size;    /* nodes: the area (2-D) or volume (3-D) of the droplet */
+    int lo[3], hi[3];/* bounding box [lo, hi) */
+} lbm_component;
+
+/* Enqueues on the context stream (no synchronisation, graph-capturable) the
+ * count of dispersed nodes of component k in box into *dev_count (an int64 in
+ * device memory owned by the caller, overwritten).  A thin box across a
+ * channel gives a time series whose rising edges are droplet passages.
+ * LBM_EINVAL for k not in {0, 1} or a box outside the domain. */
+lbm_status lbm_probe(lbm_ctx *ctx, int k, const lbm_box *box, double threshold, int64_t *dev_count);
+
+/* Synchronises and labels the face-connected components of the dispersed
+ * phase of component k in box.  *n_out receives their number; the first
+ * min(n, max_out) of them, ordered by their smallest node index, are written
+ * to out (host memory, caller owned).  Allocates and frees its own device
+ * scratch (4 bytes x 2 per node); not for use inside a graph capture. */
+lbm_status lbm_components(lbm_ctx *ctx, int k, const lbm_box *box, double threshold,
+                          lbm_component *out, int max_out, int *n_out);
+
+/* ------------------------------------------------------------------------
+ * Surrogate: an ensemble of MLPs 4 -> hidden -> hidden -> 2 (tanh) that maps
+ * the parameters of a channel run to its droplet labels.  Training (full
+ * batch, mean squared error, Adam) runs in FP32 on the GPU with hand-written
+ * forward and backward kernels; inference uses BF16 matrix cores with FP32
+ * accumulation.  A query whose members disagree (standard deviation above
+ * threshold x |mean| for an output) is flagged for the lattice Boltzmann
+ * solver.  X [n][4], Y [n][2], mean/std [n][2] and fallback [n] are device
+ * memory owned by the caller; every call only enqueues work on the context
+ * stream unless stated.
+ * ------------------------------------------------------------------------ */
+typedef struct surr_ctx surr_ctx;
+
+/* Device workspace bytes for members (1..64) of width hidden (128) trained on
+ * up to max_n samples; 0 if the arguments are invalid. */
+size_t surr_workspace_bytes(int members, int hidden, int max_n);
+
+/* Parameters per member (17410 for hidden = 128; 0 for another width). */
+int surr_param_count(int hidden);
+
+/* Initialises every member from seed (counter-based, so the same seed gives
+ * the same weights) and synchronises.  LBM_EINVAL / LBM_ENOMEM / LBM_EDEVICE
+ * as lbm_create. */
+lbm_status surr_create(int members, int hidden, int max_n, uint64_t seed, void *dev_ws, size_t ws_bytes,
+                       void *hip_stream, surr_ctx **out);
+
+/* epochs full-batch Adam steps (learning rate lr) on n <= max_n samples.  If
+ * loss_host is not NULL it synchronises and receives each member's loss
+ * before the last update. */
+lbm_status surr_train(surr_ctx *ctx, const float *X, const float *Y, int n, int epochs, float lr,
+                      float *loss_host);
+
+/* Test hook: the gradient of the loss with respect to every parameter,
+ * grads [members][P] (device), and the loss per member (device, or NULL),
+ * without updating anything. */
+lbm_status surr_forward_backward(surr_ctx *ctx, const float *X, const float *Y, int n, float *grads,
+                                 float *loss);
+
+/* Ensemble prediction of n queries: mean and standard deviation over the
+ * members of each output, and fallback[i] = 1 where some output has
+ * std > threshold * |mean|. */
+lbm_status surr_predict(surr_ctx *ctx, const float *X, int n, float *mean, float *std, uint8_t *fallback,
+                        float threshold);
+
+/* Copy every member's parameters (host float [members][P], bytes exact) out
+ * or in; both synchronise. */
+lbm_status surr_get_params(surr_ctx *ctx, float *host, size_t bytes);
+lbm_status surr_set_params(surr_ctx *ctx, const float *host, size_t bytes);
+
+/* Releases the context (not the workspace); NULL is ignored. */
+void surr_destroy(surr_ctx *ctx);
+
+/* Last error of ctx (or of the last failed surr_create if ctx is NULL). */
+const char *surr_last_error(const surr_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -117,6 +117,26 @@ def laplace(n: int = 64, R: float = 16.0, G12: float = 0.9, nu=(1.0 / 6.0, 1.0 /
     return c
 
 
+def drops(shape=(160, 64, 1), count: int = 7, seed: int = 5, r_range=(3.0, 9.0), G12: float = 0.9,
+          nu=(1.0 / 6.0, 1.0 / 6.0), major: float = 1.0, minor: float = 0.03) -> Case:
+    """Several droplets of seeded radii and centres in a periodic box (2-D when
+    shape[2] == 1): a field with many components for the labelling checks."""
+    dim = 2 if shape[2] == 1 else 3
+    c = Case("drops", dim, tuple(shape), (True, True, True), tuple(nu), G12,
+             solid=np.zeros(int(np.prod(shape)), np.uint8), rho0=None)
+    rng = np.random.default_rng(seed)
+    x, y, z = c.grid()
+    inside = np.zeros(c.N, bool)
+    for _ in range(count):
+        R = rng.uniform(*r_range)
+        cen = [rng.uniform(0, shape[a]) for a in range(3)]
+        r2 = (x - cen[0]) ** 2 + (y - cen[1]) ** 2 + ((z - cen[2]) ** 2 if dim == 3 else 0)
+        inside |= r2 < R * R
+    c.rho0 = _rho_from_mask(inside, major, minor)
+    c.meta.update(major=major, minor=minor)
+    return c
+
+
 # ---------------------------------------------------------------------------
 # Random periodic / closed boxes (for invariants and parity at several tiles)
 # ---------------------------------------------------------------------------
@@ -309,3 +329,96 @@ def coflow3d(length: int = 600, width: int = 120, inner: int = 30, u_c: float = 
 def coflow3d_quarter(**kw) -> Case:
     """The 1/4-scale copy of the co-flow device: 150 x 30 x 30 fluid, 8 x 8 inner patch."""
     return coflow3d(length=150, width=30, inner=8, **kw)
+
+
+def transpose(case: Case, axes) -> Case:
+    """The same case with its lattice axes reordered: axis a of the result is
+    axis ``axes[a]`` of ``case`` (a 3-D permutation).  Arrays, patches, the
+    body force and the initial velocity components move with the axes."""
+    assert case.dim == 3 and sorted(axes) == [0, 1, 2]
+    inv = [axes.index(a) for a in range(3)]
+    nx, ny, nz = case.n
+    n_new = tuple(case.n[a] for a in axes)
+
+    def field(v):                       # [N] in x-fastest order -> permuted
+        g = v.reshape(nz, ny, nx)      # index [z, y, x] = axis order (2, 1, 0)
+        g = g.transpose([2 - axes[2], 2 - axes[1], 2 - axes[0]])
+        return np.ascontiguousarray(g).reshape(-1)
+
+    def face(p):
+        q = dict(p)
+        q["axis"] = inv[p["axis"]]
+        q["lo"] = tuple(p["lo"][a] for a in axes)
+        q["hi"] = tuple(p["hi"][a] for a in axes)
+        return q
+
+    c = case.copy()
+    c.name = f"{case.name}_T{''.join(map(str, axes))}"
+    c.n = n_new
+    c.periodic = tuple(case.periodic[a] for a in axes)
+    c.solid = field(case.solid)
+    c.rho0 = np.stack([field(r) for r in case.rho0])
+    if case.u0 is not None:
+        c.u0 = np.stack([field(case.u0[a]) for a in axes])
+    c.Fb = tuple(case.Fb[a] for a in axes)
+    c.inlets = [face(p) for p in case.inlets]
+    c.outlet = face(case.outlet) if case.outlet is not None else None
+    return c
+
+
+# ---------------------------------------------------------------------------
+# Batched sweep of T-junctions (uneven sizes and physics)
+# ---------------------------------------------------------------------------
+
+# Interfacial tension of the G12 = 0.9 interface in lattice units, from the
+# slope of the oracle's Laplace sweep (dp against 1/R over R = 10..20 on the
+# 64 x 64 box, 2000 steps): the scale that turns a capillary number into a
+# viscosity.  tests/test_oracle_physics.py re-measures it.
+GAMMA_G09 = 0.0438
+
+
+def sweep_params(n: int = 256, seed: int = 12934, W_range=(32, 128)):
+    """Draws (W, Ca, q, M) per instance in a fixed order: W uniform integer in
+    [W_range[0], W_range[1]], log10 Ca ~ U(-3, -1), q ~ U(0.1, 2),
+    log10 M ~ U(log10 0.5, 1)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        W = int(rng.integers(W_range[0], W_range[1] + 1))
+        Ca = 10.0 ** rng.uniform(-3.0, -1.0)
+        q = rng.uniform(0.1, 2.0)
+        M = 10.0 ** rng.uniform(np.log10(0.5), 1.0)
+        out.append((W, Ca, q, M))
+    return out
+
+
+def sweep_case(W: int, Ca: float, q: float, M: float, gamma: float = GAMMA_G09, u_c: float = 0.01,
+               tau_range=(0.55, 3.0), nu_d_max: float = 1.5) -> Case:
+    """One T-junction of the sweep: main channel 8W x W, side channel of width
+    W entering at x = 1.5W and W long.  Ca = u_c rho_c nu_c / gamma sets
+    nu_c; if its relaxation time leaves tau_range the inlet velocity u_c moves
+    (within [0.002, 0.05]) instead.  nu_d = M nu_c (capped at nu_d_max),
+    u_d = q u_c (equal channel widths).  meta records every adjustment."""
+    nu_lo, nu_hi = (tau_range[0] - 0.5) / 3.0, (tau_range[1] - 0.5) / 3.0
+    nu_c = Ca * gamma / u_c
+    clamped = []
+    if nu_c < nu_lo or nu_c > nu_hi:
+        nu_c = min(max(nu_c, nu_lo), nu_hi)
+        u_c = Ca * gamma / nu_c
+        if not 0.002 <= u_c <= 0.05:
+            u_c = min(max(u_c, 0.002), 0.05)
+            clamped.append("u_c")
+    nu_d = M * nu_c
+    if nu_d > nu_d_max:
+        nu_d = nu_d_max
+        clamped.append("nu_d")
+    c = tjunction(W=W, length=8 * W, x_side=int(1.5 * W), side_width=W, side_len=W, u_c=u_c, u_d=q * u_c,
+                  nu=(nu_d, nu_c))
+    c.name = f"sweep_W{W}"
+    c.meta.update(Ca=Ca, q=q, M=M, nu_c=nu_c, nu_d=nu_d, clamped=clamped)
+    return c
+
+
+def sweep(n: int = 256, seed: int = 12934, W_range=(32, 128), **kw):
+    """The batched-sweep workload: n uneven T-junction instances."""
+    return [sweep_case(*p, **kw) for p in sweep_params(n, seed, W_range)]

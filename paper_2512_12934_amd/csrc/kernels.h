@@ -95,11 +95,11 @@ __device__ __forceinline__ int e_axis(int i, int a)
     return a == 0 ? Lat<DIM>::E[i][0] : (a == 1 ? Lat<DIM>::E[i][1] : Lat<DIM>::E[i][2]);
 }
 
-// Padded index of box node (x, y, z); x = 0 sits XOFF elements into each row
+// Padded index of box node (x, y, z); x = 0 sits xoff elements into each row
 // so that rows start on a 128-byte line (see Geometry).
 __device__ __forceinline__ int64_t pidx(const Geometry &g, int x, int y, int z)
 {
-    return (int64_t)(x + XOFF) + (int64_t)g.P[0] * ((int64_t)(y + 1) + (int64_t)g.P[1] * (int64_t)(z + 1));
+    return (int64_t)(x + g.xoff) + (int64_t)g.P[0] * ((int64_t)(y + 1) + (int64_t)g.P[1] * (int64_t)(z + 1));
 }
 
 template <int DIM>
@@ -190,35 +190,56 @@ __device__ __forceinline__ int map_axis(int v, int n, int periodic)
     return v;
 }
 
-// Deterministic block-wide sum of two doubles (256 threads, 4 waves).
-__device__ __forceinline__ void block_sum2(double &a, double &b, double *red /*[8]*/)
+// Linear index in the caller's frame of the memory-frame node (x, y, z).
+__device__ __forceinline__ int64_t caller_index(const Geometry &g, int x, int y, int z)
 {
+    return (int64_t)x * g.ostride[0] + (int64_t)y * g.ostride[1] + (int64_t)z * g.ostride[2];
+}
+
+// Deterministic block-wide sum of two doubles over NT threads (whole waves):
+// a butterfly inside each wave, then the wave sums in a fixed pairwise order.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *red /*[2 * NT / 64]*/)
+{
+    static_assert(NT % 64 == 0 && NT <= 1024, "whole waves");
+    constexpr int NW = NT / 64;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         a += __shfl_xor(a, o, 64);
         b += __shfl_xor(b, o, 64);
     }
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    __syncthreads();
-    if (ln == 0) { red[2 * wv] = a; red[2 * wv + 1] = b; }
-    __syncthreads();
-    a = (red[0] + red[2]) + (red[4] + red[6]);
-    b = (red[1] + red[3]) + (red[5] + red[7]);
+    if constexpr (NW > 1) {
+        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        __syncthreads();
+        if (ln == 0) { red[2 * wv] = a; red[2 * wv + 1] = b; }
+        __syncthreads();
+        // every thread folds the wave sums in the same fixed pairwise order
+        double ta[NW], tb[NW];
+#pragma unroll
+        for (int j = 0; j < NW; j++) { ta[j] = red[2 * j]; tb[j] = red[2 * j + 1]; }
+#pragma unroll
+        for (int w = NW / 2; w > 0; w >>= 1) {
+#pragma unroll
+            for (int j = 0; j < w; j++) { ta[j] += ta[j + w]; tb[j] += tb[j + w]; }
+        }
+        a = ta[0];
+        b = tb[0];
+    }
 }
 
 // Deterministic sum of a partials array [n][2] by every block (fixed order).
+template <int NT>
 __device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int n, double &a, double &b,
                                                 double *red)
 {
     a = 0.0;
     b = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int j = threadIdx.x; j < n; j += NT) {
         a += part[2 * j];
         b += part[2 * j + 1];
     }
-    block_sum2(a, b, red);
+    block_sum2<NT>(a, b, red);
 }
-
 
 // ---------------------------------------------------------------------------
 // k_main: the fused per-node update as a sweep along the last lattice axis
@@ -239,14 +260,12 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
 // KEEPB = 1 holds both components' populations in registers between the
 // velocity and the collision; KEEPB = 0 gathers component 2 again after
 // component 1 is stored (fewer registers, one more pass through the caches).
-template <int DIM, int STORE, int MODE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
-__global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__restrict__ src,
-                                              typename Codec<STORE>::T *__restrict__ dst,
-                                              const uint32_t *__restrict__ type,
-                                              const float2 *__restrict__ psi, Geometry g, Physics ph,
-                                              Boundary bd, int tiles_x, int tiles_y, int n_items,
-                                              double *__restrict__ out_rho, double *__restrict__ out_u,
-                                              int *__restrict__ flag)
+template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
+__device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__restrict__ src,
+                                          typename Codec<STORE>::T *__restrict__ dst,
+                                          const uint32_t *__restrict__ type, const float2 *__restrict__ psi,
+                                          const Geometry &g, const Physics &ph, const Boundary &bd, int tiles_x,
+                                          int tiles_y, int item, int *__restrict__ flag)
 {
     constexpr int Q = Lat<DIM>::Q;
     constexpr int LY = DIM == 3 ? TY : 1;          // lateral y extent of the tile
@@ -259,13 +278,10 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
     __shared__ float2 s_psi[R * PLANE];
     __shared__ uint8_t s_sol[R * PLANE];
 
-    // XCD-aware work item: blocks are dealt round-robin to the 8 XCDs
-    const int per = (int)(gridDim.x + 7) / 8;
-    const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     const __amdgpu_buffer_rsrc_t rs0 = comp_rsrc<STORE>(src, 0, Q, g.Ppad);
     const __amdgpu_buffer_rsrc_t rs1 = comp_rsrc<STORE>(src, 1, Q, g.Ppad);
-
-    if (item < n_items) {
+    __syncthreads();                               // the ring of a previous item is free
+    {
         const int ns = g.n[DIM - 1];
         const int tx = item % tiles_x;
         const int ty = (item / tiles_x) % tiles_y;
@@ -343,16 +359,7 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                 const uint32_t tw = valid ? type[b] : T_SOLID;
                 const bool fluid = !(tw & T_SOLID);
                 const bool wave_fast = __ballot(fluid && (tw & (T_BBMASK | T_EDGE))) == 0;
-                if (!fluid) {
-                    if (MODE == MODE_MOMENTS && valid) {
-                        out_rho[b] = 0.0;
-                        out_rho[g.N + b] = 0.0;
-                        out_u[b] = 0.0;
-                        out_u[g.N + b] = 0.0;
-                        out_u[2 * g.N + b] = 0.0;
-                    }
-                    continue;
-                }
+                if (!fluid) continue;
                 const uint32_t p = (uint32_t)pidx(g, x, y, DIM == 3 ? z : -1);
                 // base[d]: ring index of the lateral corner (-2, -2) of the
                 // node's neighbourhood in sweep plane sv + d - 2, so every
@@ -447,14 +454,6 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
                     u[d] = (J1[d] + J2[d] + 0.5f * (F1[d] + F2[d])) * irt;
                 });
 
-                if (MODE == MODE_MOMENTS) {
-                    out_rho[b] = r1;
-                    out_rho[g.N + b] = r2;
-                    out_u[b] = u[0];
-                    out_u[g.N + b] = u[1];
-                    out_u[2 * g.N + b] = u[2];
-                    continue;
-                }
                 if (!(rt > 0.0f) || !isfinite(rt) || !isfinite(u[0] + u[1] + u[2])) *flag = 1;
 
                 if (tw & T_ROLE) {
@@ -501,18 +500,36 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
     }
 }
 
+// One context: one block per work item (tiles that hold fluid, in tile
+// order), dealt to the XCDs in contiguous ranges.
+template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
+__global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__restrict__ src,
+                                              typename Codec<STORE>::T *__restrict__ dst,
+                                              const uint32_t *__restrict__ type,
+                                              const float2 *__restrict__ psi, Geometry g, Physics ph,
+                                              Boundary bd, int tiles_x, int tiles_y, int n_items,
+                                              const int *__restrict__ item_list, int *__restrict__ flag)
+{
+    // XCD-aware work item: blocks are dealt round-robin to the 8 XCDs
+    const int per = (int)(gridDim.x + 7) / 8;
+    const int k = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (k < n_items)
+        main_item<DIM, STORE, PSRC, TX, TY, W, ZC, KEEPB>(src, dst, type, psi, g, ph, bd, tiles_x, tiles_y,
+                                                          item_list[k], flag);
+}
+
 // ---------------------------------------------------------------------------
 // k_psi: psi_k = rho_k = sum_i f_i^k of every node (eq. 8 with psi_k = rho_k)
 // from the post-streaming populations, as float2 per box node; solid nodes
 // get (-0.0, -0.0).
 // ---------------------------------------------------------------------------
 template <int DIM, int STORE>
-__global__ __launch_bounds__(256) void k_psi(const typename Codec<STORE>::T *__restrict__ src,
+__device__ __forceinline__ void psi_body(int blk, const typename Codec<STORE>::T *__restrict__ src,
                                              const uint32_t *__restrict__ type, Geometry g,
                                              float2 *__restrict__ psi)
 {
     constexpr int Q = Lat<DIM>::Q;
-    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = (int64_t)blk * 256 + threadIdx.x;
     const bool valid = b < g.N;
     const uint32_t tw = valid ? type[b] : T_SOLID;
     const bool fluid = !(tw & T_SOLID);
@@ -531,6 +548,14 @@ __global__ __launch_bounds__(256) void k_psi(const typename Codec<STORE>::T *__r
     bgather<DIM, STORE>(comp_rsrc<STORE>(src, 1, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f);
     static_for<Q>([&](auto ic) { r2 += f[decltype(ic)::value]; });
     psi[b] = make_float2(r1, r2);
+}
+
+template <int DIM, int STORE>
+__global__ __launch_bounds__(256) void k_psi(const typename Codec<STORE>::T *__restrict__ src,
+                                             const uint32_t *__restrict__ type, Geometry g,
+                                             float2 *__restrict__ psi)
+{
+    psi_body<DIM, STORE>((int)blockIdx.x, src, type, g, psi);
 }
 
 // Density and momentum of the populations of one component.
@@ -566,14 +591,15 @@ __global__ __launch_bounds__(256) void k_moments(const typename Codec<STORE>::T 
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (b >= g.N) return;
     const uint32_t tw = type[b];
-    if (tw & T_SOLID) {
-        out_rho[b] = 0.0;
-        out_rho[g.N + b] = 0.0;
-        out_u[b] = out_u[g.N + b] = out_u[2 * g.N + b] = 0.0;
-        return;
-    }
     int x, y, z;
     coords_of(g, b, x, y, z);
+    const int64_t bo = caller_index(g, x, y, z);
+    if (tw & T_SOLID) {
+        out_rho[bo] = 0.0;
+        out_rho[g.N + bo] = 0.0;
+        out_u[bo] = out_u[g.N + bo] = out_u[2 * g.N + bo] = 0.0;
+        return;
+    }
     float g1[3] = {0.f, 0.f, 0.f}, g2[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
     static_for<(DIM == 3 ? 125 : 25)>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
@@ -604,13 +630,13 @@ __global__ __launch_bounds__(256) void k_moments(const typename Codec<STORE>::T 
     moments_of<DIM>(f, ra, Ja);
     gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, f);
     moments_of<DIM>(f, rb, Jb);
-    out_rho[b] = r1;
-    out_rho[g.N + b] = r2;
+    out_rho[bo] = r1;
+    out_rho[g.N + bo] = r2;
     static_for<3>([&](auto dc) {
         constexpr int d = decltype(dc)::value;
         const float F1 = -ph.G12 * r1 * g2[d] - ph.Gw[0] * r1 * A[d] + (r1 / rt) * ph.Fb[d];
         const float F2 = -ph.G12 * r2 * g1[d] - ph.Gw[1] * r2 * A[d] + (r2 / rt) * ph.Fb[d];
-        out_u[d * g.N + b] = (Ja[d] + Jb[d] + 0.5f * (F1 + F2)) / rt;
+        if (d < DIM) out_u[g.ax[d] * g.N + bo] = (Ja[d] + Jb[d] + 0.5f * (F1 + F2)) / rt;
     });
 }
 
@@ -622,35 +648,39 @@ __device__ __forceinline__ double chi_of(double qin, double qout)
 }
 
 // ---------------------------------------------------------------------------
-// k_outlet: eq. (23) and the collision of the outlet column with eq. (22).
+// k_chi: eq. (23).  Q_in over the inlet nodes and Q' over the x_{N-1} column,
+// from the per-node mass flows k_main left in the face slots, summed by one
+// block in the fixed record order (independent of every launch shape).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void chi_body(const Boundary &bd)
+{
+    __shared__ double s_red[2 * CHI_NT / 64];
+    double qin = 0.0, qout = 0.0;
+    for (int j = threadIdx.x; j < bd.n_in; j += CHI_NT) qin += bd.faceQ[j];
+    for (int j = threadIdx.x; j < bd.n_xp; j += CHI_NT) qout += bd.faceQ[bd.n_in + j];
+    block_sum2<CHI_NT>(qin, qout, s_red);
+    if (threadIdx.x == 0) {
+        bd.scal[SC_QIN] = qin;
+        bd.scal[SC_QOUT] = qout;
+        bd.scal[SC_CHI] = (bd.has_outlet && bd.chi_on) ? chi_of(qin, qout) : 1.0;
+    }
+}
+
+static __global__ __launch_bounds__(CHI_NT) void k_chi(Boundary bd) { chi_body(bd); }
+
+// ---------------------------------------------------------------------------
+// k_outlet: the collision of the outlet column with eq. (22), chi from k_chi.
 // ---------------------------------------------------------------------------
 template <int DIM, int STORE>
-__global__ __launch_bounds__(256) void k_outlet(const typename Codec<STORE>::T *__restrict__ src,
-                                                typename Codec<STORE>::T *__restrict__ dst,
-                                                const uint32_t *__restrict__ type, Geometry g, Physics ph,
-                                                Boundary bd, int *__restrict__ flag)
+__device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>::T *__restrict__ src,
+                                                    typename Codec<STORE>::T *__restrict__ dst,
+                                                    const uint32_t *__restrict__ type, Geometry g, Physics ph,
+                                                    Boundary bd, int *__restrict__ flag)
 {
     using T = typename Codec<STORE>::T;
     constexpr int Q = Lat<DIM>::Q;
-    __shared__ double s_red[8];
-    // eq. (23): Q_in over the inlet nodes and Q' over the x_{N-1} column, from
-    // the per-node mass flows k_main left in the face slots, summed in the
-    // fixed node order of the face records (independent of the launch shape)
-    double qin = 0.0, qout = 0.0;
-    for (int j = threadIdx.x; j < bd.n_in; j += 256) qin += bd.faceQ[bd.in[j].slot1];
-    for (int j = threadIdx.x; j < bd.n_out; j += 256) {
-        const int sp = bd.out[j].slotP;
-        if (sp >= 0) qout += bd.faceQ[sp];
-    }
-    block_sum2(qin, qout, s_red);
-    const double chi = chi_of(qin, qout);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        bd.scal[SC_QIN] = qin;
-        bd.scal[SC_QOUT] = qout;
-        bd.scal[SC_CHI] = (bd.has_outlet && bd.chi_on) ? chi : 1.0;
-    }
-    if (!bd.has_outlet || !bd.chi_on) return;
-    const int r = blockIdx.x * 256 + threadIdx.x;
+    const double chi = bd.scal[SC_CHI];
+    const int r = blk * FACE_NT + threadIdx.x;
     if (r >= bd.n_out) return;
     const OutletRec rec = bd.out[r];
     int x, y, z;
@@ -697,20 +727,29 @@ __global__ __launch_bounds__(256) void k_outlet(const typename Codec<STORE>::T *
     });
 }
 
+template <int DIM, int STORE>
+__global__ __launch_bounds__(FACE_NT) void k_outlet(const typename Codec<STORE>::T *__restrict__ src,
+                                                    typename Codec<STORE>::T *__restrict__ dst,
+                                                    const uint32_t *__restrict__ type, Geometry g, Physics ph,
+                                                    Boundary bd, int *__restrict__ flag)
+{
+    outlet_body<DIM, STORE>((int)blockIdx.x, src, dst, type, g, ph, bd, flag);
+}
+
 // ---------------------------------------------------------------------------
 // k_inlet: blocks [0, nb_in) rebuild the entering populations of the inlet
 // nodes (eqs. 13-19); blocks [nb_in, ...) sum u.n_o over x_{N-1} (eq. 21).
 // ---------------------------------------------------------------------------
 template <int DIM, int STORE>
-__global__ __launch_bounds__(256) void k_inlet(typename Codec<STORE>::T *__restrict__ dst,
-                                               const uint32_t *__restrict__ type, Geometry g, Boundary bd,
-                                               int nb_in)
+__device__ __forceinline__ void inlet_body(int blk, typename Codec<STORE>::T *__restrict__ dst,
+                                                   const uint32_t *__restrict__ type, Geometry g, Boundary bd,
+                                                   int nb_in)
 {
     using T = typename Codec<STORE>::T;
     constexpr int Q = Lat<DIM>::Q;
-    __shared__ double s_red[8];
-    if ((int)blockIdx.x < nb_in) {
-        const int r = blockIdx.x * 256 + threadIdx.x;
+    __shared__ double s_red[2 * FACE_NT / 64];
+    if ((int)blk < nb_in) {
+        const int r = blk * FACE_NT + threadIdx.x;
         if (r >= bd.n_in) return;
         const InletRec rec = bd.in[r];
         const Patch pt = bd.patch[rec.patch];
@@ -800,7 +839,7 @@ __global__ __launch_bounds__(256) void k_inlet(typename Codec<STORE>::T *__restr
         return;
     }
     // eq. (21): partial sums of the outward normal velocity over x_{N-1}
-    const int r = (blockIdx.x - nb_in) * 256 + threadIdx.x;
+    const int r = (blk - nb_in) * FACE_NT + threadIdx.x;
     double su = 0.0, cnt = 0.0;
     if (r < bd.n_out) {
         const OutletRec rec = bd.out[r];
@@ -825,34 +864,42 @@ __global__ __launch_bounds__(256) void k_inlet(typename Codec<STORE>::T *__restr
             cnt = 1.0;
         }
     }
-    block_sum2(su, cnt, s_red);
+    block_sum2<FACE_NT>(su, cnt, s_red);
     if (threadIdx.x == 0) {
-        bd.ucpart[2 * (blockIdx.x - nb_in)] = su;
-        bd.ucpart[2 * (blockIdx.x - nb_in) + 1] = cnt;
+        bd.ucpart[2 * (blk - nb_in)] = su;
+        bd.ucpart[2 * (blk - nb_in) + 1] = cnt;
     }
+}
+
+template <int DIM, int STORE>
+__global__ __launch_bounds__(FACE_NT) void k_inlet(typename Codec<STORE>::T *__restrict__ dst,
+                                                   const uint32_t *__restrict__ type, Geometry g, Boundary bd,
+                                                   int nb_in)
+{
+    inlet_body<DIM, STORE>((int)blockIdx.x, dst, type, g, bd, nb_in);
 }
 
 // ---------------------------------------------------------------------------
 // k_outlet_fill: eq. (20) for the populations entering through the outlet.
 // ---------------------------------------------------------------------------
 template <int DIM, int STORE>
-__global__ __launch_bounds__(256) void k_outlet_fill(const typename Codec<STORE>::T *__restrict__ src,
-                                                     typename Codec<STORE>::T *__restrict__ dst,
-                                                     const uint32_t *__restrict__ type, Geometry g, Boundary bd)
+__device__ __forceinline__ void outlet_fill_body(int blk, const typename Codec<STORE>::T *__restrict__ src,
+                                                         typename Codec<STORE>::T *__restrict__ dst,
+                                                         const uint32_t *__restrict__ type, Geometry g, Boundary bd)
 {
     using T = typename Codec<STORE>::T;
     constexpr int Q = Lat<DIM>::Q;
-    __shared__ double s_red[8];
+    __shared__ double s_red[2 * FACE_NT / 64];
     double su, cnt;
-    reduce_partials(bd.ucpart, bd.n_ucpart, su, cnt, s_red);
+    reduce_partials<FACE_NT>(bd.ucpart, bd.n_ucpart, su, cnt, s_red);
     double Uc = cnt > 0.0 ? su / cnt : 0.0;
     const bool clamped = Uc < 0.0;
     if (clamped) Uc = 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         bd.scal[SC_UC] = Uc;
         if (clamped) bd.scal[SC_CLAMPS] += 1.0;
     }
-    const int r = blockIdx.x * 256 + threadIdx.x;
+    const int r = blk * FACE_NT + threadIdx.x;
     if (r >= bd.n_out) return;
     const OutletRec rec = bd.out[r];
     int x, y, z;
@@ -886,6 +933,14 @@ __global__ __launch_bounds__(256) void k_outlet_fill(const typename Codec<STORE>
     });
 }
 
+template <int DIM, int STORE>
+__global__ __launch_bounds__(FACE_NT) void k_outlet_fill(const typename Codec<STORE>::T *__restrict__ src,
+                                                         typename Codec<STORE>::T *__restrict__ dst,
+                                                         const uint32_t *__restrict__ type, Geometry g, Boundary bd)
+{
+    outlet_fill_body<DIM, STORE>((int)blockIdx.x, src, dst, type, g, bd);
+}
+
 // ---------------------------------------------------------------------------
 // State exchange: canonical f[2][Q][N] (FP64) <-> population slots.
 // ---------------------------------------------------------------------------
@@ -901,12 +956,13 @@ __global__ void k_scatter(typename Codec<STORE>::T *__restrict__ dst, const uint
     int x, y, z;
     coords_of(g, b, x, y, z);
     const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
+    const int64_t bo = caller_index(g, x, y, z);
     for (int k = 0; k < 2; k++) {
         auto *dk = dst + (int64_t)k * Q * g.Ppad;
         static_for<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             Codec<STORE>::st(dk + slot_of<DIM>(g, p, tw | T_EDGE, x, y, z, i),
-                             (float)f[((int64_t)k * Q + i) * g.N + b], weight<DIM>(i));
+                             (float)f[((int64_t)k * Q + g.dmap[i]) * g.N + bo], weight<DIM>(i));
         });
     }
 }
@@ -919,19 +975,20 @@ __global__ void k_gather_state(const typename Codec<STORE>::T *__restrict__ src,
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= g.N) return;
     const uint32_t tw = type[b];
+    int x, y, z;
+    coords_of(g, b, x, y, z);
+    const int64_t bo = caller_index(g, x, y, z);
     for (int k = 0; k < 2; k++) {
         if (tw & T_SOLID) {
-            for (int i = 0; i < Q; i++) f[((int64_t)k * Q + i) * g.N + b] = 0.0;
+            for (int i = 0; i < Q; i++) f[((int64_t)k * Q + i) * g.N + bo] = 0.0;
             continue;
         }
-        int x, y, z;
-        coords_of(g, b, x, y, z);
         const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
         float v[Q];
         gather<DIM, STORE>(src + (int64_t)k * Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, v);
         static_for<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            f[((int64_t)k * Q + i) * g.N + b] = (double)v[i];
+            f[((int64_t)k * Q + g.dmap[i]) * g.N + bo] = (double)v[i];
         });
     }
 }
@@ -980,7 +1037,7 @@ __global__ __launch_bounds__(256) void k_mass(const typename Codec<STORE>::T *__
         gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, f);
         static_for<Q>([&](auto ic) { m2 += (double)f[decltype(ic)::value]; });
     }
-    block_sum2(m1, m2, s_red);
+    block_sum2<256>(m1, m2, s_red);
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = m1;
         part[2 * blockIdx.x + 1] = m2;
@@ -991,8 +1048,236 @@ static __global__ void k_reduce2(const double *__restrict__ part, int n, double 
 {
     __shared__ double s_red[8];
     double a, b;
-    reduce_partials(part, n, a, b, s_red);
+    reduce_partials<256>(part, n, a, b, s_red);
     if (threadIdx.x == 0) { out[0] = a; out[1] = b; }
+}
+
+// ---------------------------------------------------------------------------
+// Batched step: every member of a batch advanced by one launch per stage.
+// Members share the lattice, the storage and the node-update configuration
+// and differ in everything else (size, geometry, physics, faces).  The A/B
+// parity `cur` is common to all members.
+// ---------------------------------------------------------------------------
+
+// Largest i in [0, n) with start[i] <= v (start is nondecreasing, start[0] = 0).
+__device__ __forceinline__ int member_of(const int *__restrict__ start, int n, int v)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);   // uniform over the block
+}
+
+template <int DIM, int STORE>
+__global__ __launch_bounds__(256) void k_psi_batch(BatchTab t, int cur)
+{
+    using T = typename Codec<STORE>::T;
+    const int i = member_of(t.psi0, t.n, (int)blockIdx.x);
+    const Member &m = t.m[i];
+    const Geometry g = m.g;
+    psi_body<DIM, STORE>((int)blockIdx.x - t.psi0[i], (const T *)m.f[cur], m.type, g, (float2 *)m.psi);
+}
+
+// Persistent node update over the concatenated work items of all members.
+// Each XCD owns a contiguous range of the items (members are laid out one
+// after another, so an XCD works on few members at a time) and its blocks
+// stride through that range.
+template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
+__global__ __launch_bounds__(256) void k_main_batch(BatchTab t, int cur)
+{
+    using T = typename Codec<STORE>::T;
+    const int total = t.item0[t.n];
+    const int per = (total + 7) / 8;
+    const int xcd = (int)(blockIdx.x % 8), slots = (int)(gridDim.x / 8);
+    const int lo = xcd * per, hi = min(lo + per, total);
+    for (int w = lo + (int)(blockIdx.x / 8); w < hi; w += slots) {
+        const int i = member_of(t.item0, t.n, w);
+        // the member's descriptor is read-only for the whole launch: read it
+        // through a restrict pointer so the compiler may reload fields rather
+        // than hold all of them in registers
+        const Member *__restrict__ m = t.m + i;
+        main_item<DIM, STORE, PSRC, TX, TY, W, ZC, KEEPB>((const T *)m->f[cur], (T *)m->f[cur ^ 1], m->type,
+                                                          (const float2 *)m->psi, m->g, m->ph, m->bd, m->tiles_x,
+                                                          m->tiles_y, m->item_list[w - t.item0[i]], m->flag);
+    }
+}
+
+// eq. (23) sums, one block per member
+static __global__ __launch_bounds__(CHI_NT) void k_chi_batch(BatchTab t)
+{
+    const Boundary bd = t.m[blockIdx.x].bd;
+    if (bd.n_in + bd.n_out > 0) chi_body(bd);
+}
+
+template <int DIM, int STORE>
+__global__ __launch_bounds__(FACE_NT) void k_outlet_batch(BatchTab t, int cur)
+{
+    using T = typename Codec<STORE>::T;
+    const int i = member_of(t.out0, t.n, (int)blockIdx.x);
+    const Member &m = t.m[i];
+    outlet_body<DIM, STORE>((int)blockIdx.x - t.out0[i], (const T *)m.f[cur], (T *)m.f[cur ^ 1], m.type, m.g,
+                            m.ph, m.bd, m.flag);
+}
+
+template <int DIM, int STORE>
+__global__ __launch_bounds__(FACE_NT) void k_inlet_batch(BatchTab t, int cur)
+{
+    using T = typename Codec<STORE>::T;
+    const int i = member_of(t.inl0, t.n, (int)blockIdx.x);
+    const Member &m = t.m[i];
+    inlet_body<DIM, STORE>((int)blockIdx.x - t.inl0[i], (T *)m.f[cur ^ 1], m.type, m.g, m.bd, m.nb_in);
+}
+
+template <int DIM, int STORE>
+__global__ __launch_bounds__(FACE_NT) void k_outlet_fill_batch(BatchTab t, int cur)
+{
+    using T = typename Codec<STORE>::T;
+    const int i = member_of(t.fill0, t.n, (int)blockIdx.x);
+    const Member &m = t.m[i];
+    outlet_fill_body<DIM, STORE>((int)blockIdx.x - t.fill0[i], (const T *)m.f[cur], (T *)m.f[cur ^ 1], m.type,
+                                 m.g, m.bd);
+}
+
+// ---------------------------------------------------------------------------
+// Droplet labels.  The dispersed phase is the set of fluid nodes of a box
+// whose component-k density (summed from the current populations) exceeds a
+// threshold; droplets are its face-connected components.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool in_box(const Box3 &bx, int x, int y, int z)
+{
+    return x >= bx.lo[0] && x < bx.hi[0] && y >= bx.lo[1] && y < bx.hi[1] && z >= bx.lo[2] && z < bx.hi[2];
+}
+
+// rho_k of a fluid node from its post-streaming populations
+template <int DIM, int STORE>
+__device__ __forceinline__ float node_rho(const typename Codec<STORE>::T *__restrict__ src, const Geometry &g,
+                                          uint32_t tw, int x, int y, int z, int k)
+{
+    constexpr int Q = Lat<DIM>::Q;
+    float f[Q];
+    gather<DIM, STORE>(src + (int64_t)k * Q * g.Ppad, g, pidx(g, x, y, DIM == 3 ? z : -1), tw, x, y, z, f);
+    float r = 0.0f;
+    static_for<Q>([&](auto ic) { r += f[decltype(ic)::value]; });
+    return r;
+}
+
+// count of dispersed nodes in the box, added to *out (zeroed by k_zero64)
+template <int DIM, int STORE>
+__global__ __launch_bounds__(256) void k_probe(const typename Codec<STORE>::T *__restrict__ src,
+                                               const uint32_t *__restrict__ type, Geometry g, int k, Box3 bx,
+                                               float thr, unsigned long long *__restrict__ out)
+{
+    const int ex = bx.hi[0] - bx.lo[0], ey = bx.hi[1] - bx.lo[1], ez = bx.hi[2] - bx.lo[2];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int hit = 0;
+    if (v < (int64_t)ex * ey * ez) {
+        const int x = bx.lo[0] + (int)(v % ex), y = bx.lo[1] + (int)((v / ex) % ey),
+                  z = bx.lo[2] + (int)(v / ((int64_t)ex * ey));
+        const int64_t b = (int64_t)x + (int64_t)g.n[0] * ((int64_t)y + (int64_t)g.n[1] * z);
+        const uint32_t tw = type[b];
+        if (!(tw & T_SOLID)) hit = node_rho<DIM, STORE>(src, g, tw | T_EDGE, x, y, z, k) > thr;
+    }
+    const unsigned long long c = __popcll(__ballot(hit));
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+static __global__ void k_zero64(unsigned long long *p) { *p = 0ull; }
+
+// label = own box index on dispersed nodes of the box, -1 elsewhere
+template <int DIM, int STORE>
+__global__ __launch_bounds__(256) void k_lab_init(const typename Codec<STORE>::T *__restrict__ src,
+                                                  const uint32_t *__restrict__ type, Geometry g, int k, Box3 bx,
+                                                  float thr, int *__restrict__ lab)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= g.N) return;
+    int x, y, z;
+    coords_of(g, b, x, y, z);
+    const uint32_t tw = type[b];
+    bool in = !(tw & T_SOLID) && in_box(bx, x, y, z);
+    if (in) in = node_rho<DIM, STORE>(src, g, tw | T_EDGE, x, y, z, k) > thr;
+    lab[b] = in ? (int)b : -1;
+}
+
+// One pass of minimum-label propagation over face neighbours plus pointer
+// jumping (lab[lab[b]] <= lab[b]).  Labels only decrease, so passes may run
+// concurrently and in any order; the fixed point is the smallest box index
+// of each component.
+static __global__ __launch_bounds__(256) void k_lab_prop(Geometry g, int dim, int *lab, int *changed)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= g.N) return;
+    const int l = lab[b];
+    if (l < 0) return;
+    int x, y, z;
+    coords_of(g, b, x, y, z);
+    int m = l;
+    auto take = [&](int64_t nb) {
+        const int v = lab[nb];
+        if (v >= 0 && v < m) m = v;
+    };
+    if (x > 0) take(b - 1);
+    if (x + 1 < g.n[0]) take(b + 1);
+    if (y > 0) take(b - g.n[0]);
+    if (y + 1 < g.n[1]) take(b + g.n[0]);
+    if (dim == 3) {
+        const int64_t pl = (int64_t)g.n[0] * g.n[1];
+        if (z > 0) take(b - pl);
+        if (z + 1 < g.n[2]) take(b + pl);
+    }
+    const int j = lab[m];
+    if (j >= 0 && j < m) m = j;
+    if (m < l) {
+        lab[b] = m;
+        *changed = 1;
+    }
+}
+
+// roots (lab[b] == b) get consecutive slots in an arbitrary order; the host
+// orders the components afterwards
+static __global__ __launch_bounds__(256) void k_lab_roots(Geometry g, const int *__restrict__ lab,
+                                                          int *__restrict__ slot, int *__restrict__ n_roots)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= g.N) return;
+    if (lab[b] == (int)b) slot[b] = atomicAdd(n_roots, 1);
+}
+
+// per component: size, smallest caller-frame index, caller-frame bounding box
+// (integer atomics: the result does not depend on the order)
+static __global__ __launch_bounds__(256) void k_lab_stats_init(CompStat *st, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    st[i].size = 0ull;
+    st[i].first = ~0ull;
+    for (int a = 0; a < 3; a++) {
+        st[i].lo[a] = 0x7fffffff;
+        st[i].hi[a] = -1;
+    }
+}
+
+static __global__ __launch_bounds__(256) void k_lab_stats(Geometry g, const int *__restrict__ lab,
+                                                          const int *__restrict__ slot, CompStat *st)
+{
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= g.N) return;
+    const int l = lab[b];
+    if (l < 0) return;
+    CompStat *c = st + slot[l];
+    int x, y, z;
+    coords_of(g, b, x, y, z);
+    const int mc[3] = {x, y, z};
+    atomicAdd(&c->size, 1ull);
+    atomicMin(&c->first, (unsigned long long)caller_index(g, x, y, z));
+    for (int a = 0; a < 3; a++) {
+        atomicMin(&c->lo[g.ax[a]], mc[a]);
+        atomicMax(&c->hi[g.ax[a]], mc[a] + 1);
+    }
 }
 
 }  // namespace lbm

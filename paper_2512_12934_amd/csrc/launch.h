@@ -49,16 +49,26 @@ struct StepArgs {
     Physics ph;
     Boundary bd;
     int tiles_x, tiles_y, items;
+    const int *item_list;
     unsigned grid;
     double *orho, *ou;
     int *flag;
     hipStream_t stream;
 };
 
+// One step of a whole batch: launch sizes of each stage (0 = skip).
+struct BatchArgs {
+    BatchTab t;
+    int cur;
+    unsigned g_psi, g_main, g_chi, g_out, g_inl, g_fill;
+    hipStream_t stream;
+};
+
 template <int DIM> struct Launcher {
     static void psi(int storage, const StepArgs &a);
     static void moments(int storage, const StepArgs &a);
-    static void main(int storage, int cfg, int mode, const StepArgs &a);
+    static void main(int storage, int cfg, const StepArgs &a);
+    static void chi(const StepArgs &a);
     static void outlet(int storage, const StepArgs &a, unsigned nb);
     static void inlet(int storage, const StepArgs &a, unsigned nb, int nb_in);
     static void outlet_fill(int storage, const StepArgs &a, unsigned nb);
@@ -66,6 +76,13 @@ template <int DIM> struct Launcher {
     static void gather_state(int storage, const StepArgs &a, double *f);
     static void feq_state(const double *rho0, const double *u0, int64_t N, double *f, hipStream_t s);
     static void mass(int storage, const StepArgs &a, double *part, int nb, double *out);
+    static void batch_step(int storage, int cfg, const BatchArgs &b);
+    // droplet labels
+    static void probe(int storage, const StepArgs &a, int k, const Box3 &bx, float thr, unsigned long long *out);
+    static void lab_init(int storage, const StepArgs &a, int k, const Box3 &bx, float thr, int *lab);
+    static void lab_prop(const StepArgs &a, int *lab, int *changed, int passes);
+    static void lab_roots(const StepArgs &a, const int *lab, int *slot, int *n_roots);
+    static void lab_stats(const StepArgs &a, const int *lab, const int *slot, CompStat *st, int n);
 };
 
 extern template struct Launcher<2>;

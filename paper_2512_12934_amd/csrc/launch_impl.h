@@ -14,20 +14,45 @@ namespace detail {
 template <int DIM> constexpr const TileCfg &cfg_at(int i) { return DIM == 2 ? CFG2[i] : CFG3[i]; }
 template <int DIM> constexpr int cfg_count() { return DIM == 2 ? NCFG2 : NCFG3; }
 
-template <int DIM, int STORE, int MODE, int I>
+template <int DIM, int STORE, int I>
 void launch_cfg(const StepArgs &a)
 {
     constexpr TileCfg c = cfg_at<DIM>(I);
     using T = typename Codec<STORE>::T;
-    hipLaunchKernelGGL((k_main<DIM, STORE, MODE, c.psrc, c.tx, c.ty, c.w, c.zc, c.keepb>), dim3(a.grid), dim3(256),
-                       0, a.stream, (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.g, a.ph, a.bd,
-                       a.tiles_x, a.tiles_y, a.items, a.orho, a.ou, a.flag);
+    hipLaunchKernelGGL((k_main<DIM, STORE, c.psrc, c.tx, c.ty, c.w, c.zc, c.keepb>), dim3(a.grid), dim3(256), 0,
+                       a.stream, (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.g, a.ph, a.bd,
+                       a.tiles_x, a.tiles_y, a.items, a.item_list, a.flag);
 }
 
 template <int DIM, int STORE, int... I>
 void launch_step_cfg(int cfg, const StepArgs &a, std::integer_sequence<int, I...>)
 {
-    ((cfg == I ? launch_cfg<DIM, STORE, MODE_STEP, I>(a) : void()), ...);
+    ((cfg == I ? launch_cfg<DIM, STORE, I>(a) : void()), ...);
+}
+
+template <int DIM, int STORE, int I>
+void launch_batch_cfg(const BatchArgs &b)
+{
+    constexpr TileCfg c = cfg_at<DIM>(I);
+    if (c.psrc && b.g_psi)
+        hipLaunchKernelGGL((k_psi_batch<DIM, STORE>), dim3(b.g_psi), dim3(256), 0, b.stream, b.t, b.cur);
+    if (b.g_main)
+        hipLaunchKernelGGL((k_main_batch<DIM, STORE, c.psrc, c.tx, c.ty, c.w, c.zc, c.keepb>), dim3(b.g_main),
+                           dim3(256), 0, b.stream, b.t, b.cur);
+    if (b.g_chi) hipLaunchKernelGGL(k_chi_batch, dim3(b.g_chi), dim3(CHI_NT), 0, b.stream, b.t);
+    if (b.g_out)
+        hipLaunchKernelGGL((k_outlet_batch<DIM, STORE>), dim3(b.g_out), dim3(FACE_NT), 0, b.stream, b.t, b.cur);
+    if (b.g_inl)
+        hipLaunchKernelGGL((k_inlet_batch<DIM, STORE>), dim3(b.g_inl), dim3(FACE_NT), 0, b.stream, b.t, b.cur);
+    if (b.g_fill)
+        hipLaunchKernelGGL((k_outlet_fill_batch<DIM, STORE>), dim3(b.g_fill), dim3(FACE_NT), 0, b.stream, b.t,
+                           b.cur);
+}
+
+template <int DIM, int STORE, int... I>
+void launch_batch(int cfg, const BatchArgs &b, std::integer_sequence<int, I...>)
+{
+    ((cfg == I ? launch_batch_cfg<DIM, STORE, I>(b) : void()), ...);
 }
 
 }  // namespace detail
@@ -56,22 +81,27 @@ void Launcher<DIM>::moments(int storage, const StepArgs &a)
 }
 
 template <int DIM>
-void Launcher<DIM>::main(int storage, int cfg, int mode, const StepArgs &a)
+void Launcher<DIM>::main(int storage, int cfg, const StepArgs &a)
 {
     constexpr int N = detail::cfg_count<DIM>();
-    (void)mode;   // the node update only runs time steps; moments use k_moments
     if (storage == 0) detail::launch_step_cfg<DIM, 0>(cfg, a, std::make_integer_sequence<int, N>{});
     else detail::launch_step_cfg<DIM, 1>(cfg, a, std::make_integer_sequence<int, N>{});
+}
+
+template <int DIM>
+void Launcher<DIM>::chi(const StepArgs &a)
+{
+    hipLaunchKernelGGL(k_chi, dim3(1), dim3(CHI_NT), 0, a.stream, a.bd);
 }
 
 template <int DIM>
 void Launcher<DIM>::outlet(int storage, const StepArgs &a, unsigned nb)
 {
     if (storage == 0)
-        hipLaunchKernelGGL((k_outlet<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, (float *)a.dst,
+        hipLaunchKernelGGL((k_outlet<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const float *)a.src, (float *)a.dst,
                            a.type, a.g, a.ph, a.bd, a.flag);
     else
-        hipLaunchKernelGGL((k_outlet<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src,
+        hipLaunchKernelGGL((k_outlet<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const __half *)a.src,
                            (__half *)a.dst, a.type, a.g, a.ph, a.bd, a.flag);
 }
 
@@ -79,10 +109,10 @@ template <int DIM>
 void Launcher<DIM>::inlet(int storage, const StepArgs &a, unsigned nb, int nb_in)
 {
     if (storage == 0)
-        hipLaunchKernelGGL((k_inlet<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (float *)a.dst, a.type, a.g, a.bd,
+        hipLaunchKernelGGL((k_inlet<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (float *)a.dst, a.type, a.g, a.bd,
                            nb_in);
     else
-        hipLaunchKernelGGL((k_inlet<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (__half *)a.dst, a.type, a.g, a.bd,
+        hipLaunchKernelGGL((k_inlet<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (__half *)a.dst, a.type, a.g, a.bd,
                            nb_in);
 }
 
@@ -90,10 +120,10 @@ template <int DIM>
 void Launcher<DIM>::outlet_fill(int storage, const StepArgs &a, unsigned nb)
 {
     if (storage == 0)
-        hipLaunchKernelGGL((k_outlet_fill<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src,
+        hipLaunchKernelGGL((k_outlet_fill<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const float *)a.src,
                            (float *)a.dst, a.type, a.g, a.bd);
     else
-        hipLaunchKernelGGL((k_outlet_fill<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src,
+        hipLaunchKernelGGL((k_outlet_fill<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const __half *)a.src,
                            (__half *)a.dst, a.type, a.g, a.bd);
 }
 
@@ -136,6 +166,63 @@ void Launcher<DIM>::mass(int storage, const StepArgs &a, double *part, int nb, d
         hipLaunchKernelGGL((k_mass<DIM, 1>), dim3((unsigned)nb), dim3(256), 0, a.stream, (const __half *)a.src,
                            a.type, a.g, part);
     hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, a.stream, (const double *)part, nb, out);
+}
+
+template <int DIM>
+void Launcher<DIM>::probe(int storage, const StepArgs &a, int k, const Box3 &bx, float thr, unsigned long long *out)
+{
+    const int64_t vol = (int64_t)(bx.hi[0] - bx.lo[0]) * (bx.hi[1] - bx.lo[1]) * (bx.hi[2] - bx.lo[2]);
+    hipLaunchKernelGGL(k_zero64, dim3(1), dim3(1), 0, a.stream, out);
+    if (vol <= 0) return;
+    const unsigned nb = (unsigned)((vol + 255) / 256);
+    if (storage == 0)
+        hipLaunchKernelGGL((k_probe<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.g, k,
+                           bx, thr, out);
+    else
+        hipLaunchKernelGGL((k_probe<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type, a.g,
+                           k, bx, thr, out);
+}
+
+template <int DIM>
+void Launcher<DIM>::lab_init(int storage, const StepArgs &a, int k, const Box3 &bx, float thr, int *lab)
+{
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    if (storage == 0)
+        hipLaunchKernelGGL((k_lab_init<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.g,
+                           k, bx, thr, lab);
+    else
+        hipLaunchKernelGGL((k_lab_init<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
+                           a.g, k, bx, thr, lab);
+}
+
+template <int DIM>
+void Launcher<DIM>::lab_prop(const StepArgs &a, int *lab, int *changed, int passes)
+{
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    for (int p = 0; p < passes; p++) hipLaunchKernelGGL(k_lab_prop, dim3(nb), dim3(256), 0, a.stream, a.g, DIM, lab, changed);
+}
+
+template <int DIM>
+void Launcher<DIM>::lab_roots(const StepArgs &a, const int *lab, int *slot, int *n_roots)
+{
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    hipLaunchKernelGGL(k_lab_roots, dim3(nb), dim3(256), 0, a.stream, a.g, lab, slot, n_roots);
+}
+
+template <int DIM>
+void Launcher<DIM>::lab_stats(const StepArgs &a, const int *lab, const int *slot, CompStat *st, int n)
+{
+    if (n > 0) hipLaunchKernelGGL(k_lab_stats_init, dim3((n + 255) / 256), dim3(256), 0, a.stream, st, n);
+    const unsigned nb = (unsigned)((a.g.N + 255) / 256);
+    hipLaunchKernelGGL(k_lab_stats, dim3(nb), dim3(256), 0, a.stream, a.g, lab, slot, st);
+}
+
+template <int DIM>
+void Launcher<DIM>::batch_step(int storage, int cfg, const BatchArgs &b)
+{
+    constexpr int N = detail::cfg_count<DIM>();
+    if (storage == 0) detail::launch_batch<DIM, 0>(cfg, b, std::make_integer_sequence<int, N>{});
+    else detail::launch_batch<DIM, 1>(cfg, b, std::make_integer_sequence<int, N>{});
 }
 
 }  // namespace lbm

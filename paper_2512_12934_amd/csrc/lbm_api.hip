@@ -33,7 +33,8 @@ struct Layout {
     int dim = 0, Q = 0, storage = 0;
     Geometry g{};
     int tiles[3] = {1, 1, 1};      // lateral x tiles, lateral y tiles, sweep chunks
-    int64_t nblocks_main = 0;      // work items of the node update
+    int64_t nblocks_main = 0;      // work items of the node update (tiles holding fluid)
+    std::vector<int> item_list;    // their tile indices
     int64_t grid_main = 0;         // launched blocks (a multiple of 8)
     int64_t n_slots = 0, n_in = 0, n_out = 0;
     int nb_in = 0, nb_out = 0;
@@ -41,7 +42,7 @@ struct Layout {
     bool boundary = false;
     // byte offsets into the workspace
     size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
-        o_flag, o_mpart, o_mout, o_patch, o_psi, total;
+        o_flag, o_mpart, o_mout, o_patch, o_psi, o_items, total;
     int cfg = 0;                   // node-update configuration (launch.h)
     int psi_mode = 1;              // 1: psi array written by k_psi, 0: recomputed in k_main
 };
@@ -52,9 +53,27 @@ struct Maps {
     std::vector<int32_t> bslot;
     std::vector<InletRec> in;
     std::vector<OutletRec> out;
+    int n_xp = 0;                  // fluid x_{N-1} nodes (slots n_in .. n_in + n_xp)
 };
 
 int lat_Q(int dim) { return dim == 2 ? 9 : 19; }
+
+// Row layout of the population planes: elements per 128-byte line, the
+// offset of x = 0 (the start of the second line of the row, so every row is
+// line-aligned and the ghost slot x = -1 ends the first line) and the
+// padded row pitch.
+int line_elems(int storage) { return storage == LBM_STORE_F32 ? 32 : 64; }
+int row_xoff(int storage)
+{
+    const char *e = getenv("LBM_XOFF_MODE");
+    if (e && atoi(e) == 0) return 32;
+    return line_elems(storage);
+}
+int row_pitch(int n0, int storage)
+{
+    const int le = line_elems(storage);
+    return (row_xoff(storage) + n0 + 1 + le - 1) / le * le;
+}
 
 template <int DIM> void lat_e(int i, int *e)
 {
@@ -78,6 +97,79 @@ bool on_face(const lbm_config *c, const int *xc, int axis, int side, const int *
     return true;
 }
 
+// The configuration in memory axis order.  With LBM_LAYOUT_FACE_LAST (3-D)
+// the axis normal to the open faces (the outlet's, else the first inlet's)
+// becomes the last memory axis, so the face nodes of the inlet and outlet
+// kernels are contiguous planes instead of single elements strided by a row.  The lattice is closed under
+// axis permutations and the collision operator commutes with them (equal
+// rates within every moment group of one tensor order), so the permuted
+// problem is the same problem; only entry and exit of state are remapped.
+struct Canon {
+    lbm_config c{};
+    int ax[3] = {0, 1, 2};         // memory axis a holds the caller's axis ax[a]
+    std::vector<uint8_t> solid;
+};
+
+std::string canonicalize(const lbm_config *in, Canon &k)
+{
+    if (!in) return "null configuration";
+    if (in->dim != 2 && in->dim != 3) return "dim must be 2 or 3";
+    if (in->dim == 2 && in->n[2] != 1) return "2-D boxes need n[2] == 1";
+    for (int a = 0; a < in->dim; a++)
+        if (in->n[a] < 3 || in->n[a] > (1 << 24)) return "every lattice axis needs 3 .. 2^24 nodes";
+    if (!in->solid || !in->rho0) return "solid and rho0 arrays are required";
+    const int64_t N = (int64_t)in->n[0] * in->n[1] * (in->dim == 3 ? in->n[2] : 1);
+    for (int64_t b = 0; b < N; b++) {
+        if (in->solid[b]) continue;
+        if (!(in->rho0[b] > 0.0) || !(in->rho0[N + b] > 0.0))
+            return "initial densities must be positive on fluid nodes";
+    }
+    int flow = -1;
+    if (in->layout != LBM_LAYOUT_CALLER && in->layout != LBM_LAYOUT_FACE_LAST) return "unknown layout";
+    if (in->dim == 3 && in->layout == LBM_LAYOUT_FACE_LAST) {
+        if (in->has_outlet && in->outlet.axis >= 0 && in->outlet.axis < 3) flow = in->outlet.axis;
+        else if (in->n_inlets > 0 && in->inlets[0].axis >= 0 && in->inlets[0].axis < 3) flow = in->inlets[0].axis;
+    }
+    if (flow >= 0 && flow != 2) {
+        int j = 0;
+        for (int a = 0; a < 3; a++)
+            if (a != flow) k.ax[j++] = a;
+        k.ax[2] = flow;
+    }
+    int inv[3];
+    for (int a = 0; a < 3; a++) inv[k.ax[a]] = a;
+    k.c = *in;
+    lbm_config &c = k.c;
+    for (int a = 0; a < 3; a++) {
+        c.n[a] = in->n[k.ax[a]];
+        c.periodic[a] = in->periodic[k.ax[a]];
+        c.Fb[a] = in->Fb[k.ax[a]];
+    }
+    auto remap_face = [&](int &axis, int *lo, int *hi) {
+        if (axis >= 0 && axis < 3) axis = inv[axis];
+        int l[3], h[3];
+        for (int a = 0; a < 3; a++) { l[a] = lo[k.ax[a]]; h[a] = hi[k.ax[a]]; }
+        for (int a = 0; a < 3; a++) { lo[a] = l[a]; hi[a] = h[a]; }
+    };
+    for (int q = 0; q < c.n_inlets && q < LBM_MAX_INLETS; q++) remap_face(c.inlets[q].axis, c.inlets[q].lo, c.inlets[q].hi);
+    if (c.has_outlet) remap_face(c.outlet.axis, c.outlet.lo, c.outlet.hi);
+    if (k.ax[0] == 0 && k.ax[1] == 1 && k.ax[2] == 2) {
+        c.solid = in->solid;
+    } else {
+        k.solid.resize(N);
+        const int64_t st[3] = {1, in->n[0], (int64_t)in->n[0] * in->n[1]};
+        const int64_t os[3] = {st[k.ax[0]], st[k.ax[1]], st[k.ax[2]]};
+        int64_t b = 0;
+        for (int z = 0; z < c.n[2]; z++)
+            for (int y = 0; y < c.n[1]; y++)
+                for (int x = 0; x < c.n[0]; x++, b++) k.solid[b] = in->solid[x * os[0] + y * os[1] + z * os[2]];
+        c.solid = k.solid.data();
+    }
+    // rho0 / u0 stay in the caller's frame: the initial state is built there
+    // and scattered through the frame map
+    return "";
+}
+
 // Validates the configuration and builds the node maps.  Returns an empty
 // string on success, else the reason.
 std::string build_maps(const lbm_config *c, Maps &m)
@@ -96,7 +188,7 @@ std::string build_maps(const lbm_config *c, Maps &m)
     if (c->s_eps_policy != LBM_SEPS_MAXVISC && c->s_eps_policy != LBM_SEPS_FIXED) return "unknown s_eps policy";
     if (c->n_inlets < 0 || c->n_inlets > LBM_MAX_INLETS) return "bad inlet count";
     if (c->tile_config < -1 || c->tile_config >= n_tile_cfg(c->dim)) return "unknown tile configuration";
-    if (!c->solid || !c->rho0) return "solid and rho0 arrays are required";
+    if (!c->solid) return "the solid array is required";
     for (int q = 0; q < c->n_inlets; q++) {
         const lbm_inlet &p = c->inlets[q];
         if (p.axis < 0 || p.axis >= c->dim || (p.side != 0 && p.side != 1)) return "bad inlet face";
@@ -112,7 +204,7 @@ std::string build_maps(const lbm_config *c, Maps &m)
     const int Q = lat_Q(c->dim);
     {
         // each component array is addressed with 32-bit byte offsets
-        const int64_t pad = (int64_t)((c->n[0] + XOFF + 1 + 31) / 32 * 32) * (c->n[1] + 2) *
+        const int64_t pad = (int64_t)row_pitch(c->n[0], c->storage) * (c->n[1] + 2) *
                             (c->dim == 3 ? c->n[2] + 2 : 1);
         const int64_t bytes = pad * Q * (c->storage == LBM_STORE_F32 ? 4 : 2);
         if (bytes >= ((int64_t)1 << 31)) return "domain too large for one context (2 GiB per component array)";
@@ -227,9 +319,19 @@ std::string build_maps(const lbm_config *c, Maps &m)
             m.out.push_back(r);
         }
     }
+    // face slots: the inlet nodes in record order, then the fluid x_{N-1}
+    // nodes in outlet record order (so the eq. 23 sums read two contiguous
+    // ranges in a fixed order), then every other role node in box order
     int32_t slot = 0;
+    for (auto &r : m.in) m.bslot[r.b1] = slot++;
+    m.n_xp = 0;
+    for (auto &r : m.out)
+        if (r.bP >= 0 && m.bslot[r.bP] < 0) {
+            m.bslot[r.bP] = slot++;
+            m.n_xp++;
+        }
     for (int64_t b = 0; b < N; b++)
-        if (m.type[b] & T_ROLE) m.bslot[b] = slot++;
+        if ((m.type[b] & T_ROLE) && m.bslot[b] < 0) m.bslot[b] = slot++;
     for (auto &r : m.in) {
         r.slot1 = m.bslot[r.b1];
         r.slot2 = c->solid[r.b2] ? r.slot1 : m.bslot[r.b2];
@@ -238,11 +340,6 @@ std::string build_maps(const lbm_config *c, Maps &m)
         r.slotN = m.bslot[r.bN];
         r.slotP = r.bP >= 0 ? m.bslot[r.bP] : -1;
         if (r.bP < 0) r.bP = r.bN;
-    }
-    for (int64_t b = 0; b < N; b++) {
-        if (c->solid[b]) continue;
-        for (int k = 0; k < 2; k++)
-            if (!(c->rho0[k * N + b] > 0.0)) return "initial densities must be positive on fluid nodes";
     }
     return "";
 }
@@ -255,8 +352,9 @@ int default_cfg(const lbm_config *c)
     return 0;
 }
 
-Layout make_layout(const lbm_config *c, const Maps &m)
+Layout make_layout(const Canon &k, const Maps &m)
 {
+    const lbm_config *c = &k.c;
     Layout L;
     L.dim = c->dim;
     L.Q = lat_Q(c->dim);
@@ -264,11 +362,34 @@ Layout make_layout(const lbm_config *c, const Maps &m)
     Geometry &g = L.g;
     for (int a = 0; a < 3; a++) {
         g.n[a] = a < c->dim ? c->n[a] : 1;
-        g.P[a] = a == 0 ? (c->n[0] + XOFF + 1 + 31) / 32 * 32 : (a < c->dim ? c->n[a] + 2 : 1);
+        g.P[a] = a == 0 ? row_pitch(c->n[0], c->storage) : (a < c->dim ? c->n[a] + 2 : 1);
         g.periodic[a] = a < c->dim ? (c->periodic[a] != 0) : 1;
     }
     g.N = (int64_t)g.n[0] * g.n[1] * g.n[2];
     g.Ppad = (int64_t)g.P[0] * g.P[1] * g.P[2];
+    g.xoff = row_xoff(c->storage);
+    {
+        // the caller's frame
+        int on[3];
+        for (int a = 0; a < 3; a++) on[k.ax[a]] = g.n[a];
+        const int64_t st[3] = {1, on[0], (int64_t)on[0] * on[1]};
+        for (int a = 0; a < 3; a++) {
+            g.ax[a] = k.ax[a];
+            g.ostride[a] = st[k.ax[a]];
+        }
+        const int Q = lat_Q(c->dim);
+        for (int i = 0; i < 19; i++) g.dmap[i] = (signed char)i;
+        for (int i = 0; i < Q; i++) {
+            int e[3], p[3];
+            dir(c->dim, i, e);
+            for (int a = 0; a < 3; a++) p[k.ax[a]] = e[a];
+            for (int j = 0; j < Q; j++) {
+                int f[3];
+                dir(c->dim, j, f);
+                if (f[0] == p[0] && f[1] == p[1] && f[2] == p[2]) g.dmap[i] = (signed char)j;
+            }
+        }
+    }
     L.cfg = c->tile_config >= 0 ? c->tile_config : default_cfg(c);
     const TileCfg &tc = tile_cfg(c->dim, L.cfg);
     L.psi_mode = tc.psrc;
@@ -281,15 +402,34 @@ Layout make_layout(const lbm_config *c, const Maps &m)
         L.tiles[1] = (g.n[1] + tc.ty - 1) / tc.ty;
         L.tiles[2] = (g.n[2] + tc.zc - 1) / tc.zc;
     }
-    L.nblocks_main = (int64_t)L.tiles[0] * L.tiles[1] * L.tiles[2];
-    L.grid_main = (L.nblocks_main + 7) / 8 * 8;
+    // the work list: every tile that holds a fluid node (all-solid tiles,
+    // common in channel networks, are never launched)
+    {
+        const int64_t all = (int64_t)L.tiles[0] * L.tiles[1] * L.tiles[2];
+        std::vector<uint8_t> live(all, 0);
+        const int ny = c->dim == 3 ? g.n[1] : 1, nz = c->dim == 3 ? g.n[2] : g.n[1];
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < ny; y++)
+                for (int x = 0; x < g.n[0]; x++) {
+                    const int64_t b = (int64_t)x + (int64_t)g.n[0] * ((int64_t)y + (int64_t)ny * z);
+                    if (m.type[b] & T_SOLID) continue;
+                    const int64_t it = x / tc.tx + (int64_t)L.tiles[0] * ((c->dim == 3 ? y / tc.ty : 0) +
+                                                                          (int64_t)L.tiles[1] * (z / tc.zc));
+                    live[it] = 1;
+                }
+        L.item_list.clear();
+        for (int64_t it = 0; it < all; it++)
+            if (live[it]) L.item_list.push_back((int)it);
+    }
+    L.nblocks_main = (int64_t)L.item_list.size();
+    L.grid_main = std::max<int64_t>((L.nblocks_main + 7) / 8 * 8, 8);
     L.n_in = (int64_t)m.in.size();
     L.n_out = (int64_t)m.out.size();
     L.n_slots = 0;
     for (auto s : m.bslot) L.n_slots = std::max<int64_t>(L.n_slots, s + 1);
     L.boundary = L.n_in > 0 || c->has_outlet;
-    L.nb_in = (int)((L.n_in + 255) / 256);
-    L.nb_out = (int)((L.n_out + 255) / 256);
+    L.nb_in = (int)((L.n_in + FACE_NT - 1) / FACE_NT);
+    L.nb_out = (int)((L.n_out + FACE_NT - 1) / FACE_NT);
     L.nb_mass = (int)std::min<int64_t>(1024, (g.N + 255) / 256);
     const size_t fbytes = (size_t)2 * L.Q * g.Ppad * (L.storage == LBM_STORE_F32 ? 4 : 2);
     size_t o = 0;
@@ -310,6 +450,7 @@ Layout make_layout(const lbm_config *c, const Maps &m)
     L.o_mout = take(16);
     L.o_patch = take(sizeof(Patch) * MAX_PATCH);
     L.o_psi = take((size_t)g.N * 8);
+    L.o_items = take(L.item_list.size() * 4);
     L.total = o;
     return L;
 }
@@ -328,6 +469,18 @@ struct lbm_ctx {
     double mass0[2] = {0, 0};
     bool unstable = false;
     std::string err;
+    // Step loop as a replayed HIP graph: graph_steps steps per graph, one
+    // executable per parity of the A/B arrays at its start, captured on a
+    // private stream the first time it is needed.
+    int graph_steps = 16;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gx[2] = {nullptr, nullptr};
+    ~lbm_ctx()
+    {
+        for (auto &g : gx)
+            if (g) (void)hipGraphExecDestroy(g);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
     void *fsrc() const { return ws + (cur == 0 ? L.o_fA : L.o_fB); }
     void *fdst() const { return ws + (cur == 0 ? L.o_fB : L.o_fA); }
     const uint32_t *type() const { return (const uint32_t *)(ws + L.o_type); }
@@ -364,6 +517,7 @@ StepArgs step_args(const lbm_ctx *c, double *orho = nullptr, double *ou = nullpt
     a.tiles_x = L.tiles[0];
     a.tiles_y = L.tiles[1];
     a.items = (int)L.nblocks_main;
+    a.item_list = (const int *)(c->ws + L.o_items);
     a.grid = (unsigned)L.grid_main;
     a.orho = orho;
     a.ou = ou;
@@ -384,17 +538,17 @@ template <int DIM> struct Ops {
     }
 
     // ev (optional): events bracketing k_psi (ev[8], ev[9]) and k_main (ev[0], ev[1])
-    static void main_kernel(lbm_ctx *c, int mode, double *orho, double *ou, hipEvent_t *ev = nullptr)
+    static void main_kernel(lbm_ctx *c, hipEvent_t *ev = nullptr)
     {
         const Layout &L = c->L;
-        StepArgs a = step_args(c, orho, ou);
+        StepArgs a = step_args(c);
         if (L.psi_mode) {
             if (ev) (void)hipEventRecord(ev[8], c->stream);
             Lx::psi(L.storage, a);
             if (ev) (void)hipEventRecord(ev[9], c->stream);
         }
         if (ev) (void)hipEventRecord(ev[0], c->stream);
-        Lx::main(L.storage, L.cfg, mode, a);
+        Lx::main(L.storage, L.cfg, a);
         if (ev) (void)hipEventRecord(ev[1], c->stream);
     }
 
@@ -402,12 +556,12 @@ template <int DIM> struct Ops {
     static void step(lbm_ctx *c, hipEvent_t *ev = nullptr)
     {
         const Layout &L = c->L;
-        main_kernel(c, MODE_STEP, nullptr, nullptr, ev);
+        main_kernel(c, ev);
         if (L.boundary) {
             const StepArgs a = step_args(c);
-            const unsigned nb = (unsigned)std::max(L.nb_out, 1);
             if (ev) (void)hipEventRecord(ev[2], c->stream);
-            Lx::outlet(L.storage, a, nb);
+            Lx::chi(a);
+            if (c->bd.has_outlet && c->bd.chi_on && L.nb_out > 0) Lx::outlet(L.storage, a, (unsigned)L.nb_out);
             if (ev) (void)hipEventRecord(ev[3], c->stream);
             if (L.nb_in + L.nb_out > 0) {
                 if (ev) (void)hipEventRecord(ev[4], c->stream);
@@ -466,19 +620,26 @@ extern "C" {
 
 size_t lbm_workspace_bytes(const lbm_config *cfg)
 {
+    Canon k;
+    if (!canonicalize(cfg, k).empty()) return 0;
     Maps m;
-    if (!build_maps(cfg, m).empty()) return 0;
-    return make_layout(cfg, m).total;
+    if (!build_maps(&k.c, m).empty()) return 0;
+    return make_layout(k, m).total;
 }
 
 lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void *hip_stream, lbm_ctx **out)
 {
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
     *out = nullptr;
-    Maps m;
-    const std::string why = build_maps(cfg, m);
+    Canon canon;
+    std::string why = canonicalize(cfg, canon);
     if (!why.empty()) return fail(nullptr, LBM_EINVAL, why);
-    Layout L = make_layout(cfg, m);
+    const double *rho0 = cfg->rho0, *u0 = cfg->u0;   // caller's frame
+    cfg = &canon.c;                                   // memory frame from here on
+    Maps m;
+    why = build_maps(cfg, m);
+    if (!why.empty()) return fail(nullptr, LBM_EINVAL, why);
+    Layout L = make_layout(canon, m);
     if (!dev_ws) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
     if (((uintptr_t)dev_ws) % ALIGN) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < L.total) return fail(nullptr, LBM_ENOMEM, "workspace too small");
@@ -531,6 +692,7 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
     bd.in = (const InletRec *)(ws + L.o_in);
     bd.out = (const OutletRec *)(ws + L.o_out);
     bd.bslot = (const int *)(ws + L.o_bslot);
+    bd.n_xp = m.n_xp;
     bd.faceF = (float *)(ws + L.o_faceF);
     bd.faceU = (float *)(ws + L.o_faceU);
     bd.faceQ = (double *)(ws + L.o_qpart);
@@ -549,16 +711,19 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
         if (L.n_out)
             HIPCHECK(c, hipMemcpyAsync(ws + L.o_out, m.out.data(), m.out.size() * sizeof(OutletRec), hipMemcpyHostToDevice, s));
         HIPCHECK(c, hipMemcpyAsync(ws + L.o_patch, patches, sizeof patches, hipMemcpyHostToDevice, s));
+        if (!L.item_list.empty())
+            HIPCHECK(c, hipMemcpyAsync(ws + L.o_items, L.item_list.data(), L.item_list.size() * 4,
+                                       hipMemcpyHostToDevice, s));
         const double one = 1.0;
         HIPCHECK(c, hipMemcpyAsync(ws + L.o_scal + SC_CHI * 8, &one, 8, hipMemcpyHostToDevice, s));
         // initial state f = feq(rho0, u0), scattered into the source slots
         const int64_t N = L.g.N;
         double *d_rho = nullptr, *d_u = nullptr, *d_f = nullptr;
         HIPCHECK(c, hipMalloc(&d_rho, (size_t)2 * N * 8));
-        if (cfg->u0) HIPCHECK(c, hipMalloc(&d_u, (size_t)3 * N * 8));
+        if (u0) HIPCHECK(c, hipMalloc(&d_u, (size_t)3 * N * 8));
         HIPCHECK(c, hipMalloc(&d_f, (size_t)2 * L.Q * N * 8));
-        HIPCHECK(c, hipMemcpyAsync(d_rho, cfg->rho0, (size_t)2 * N * 8, hipMemcpyHostToDevice, s));
-        if (cfg->u0) HIPCHECK(c, hipMemcpyAsync(d_u, cfg->u0, (size_t)3 * N * 8, hipMemcpyHostToDevice, s));
+        HIPCHECK(c, hipMemcpyAsync(d_rho, rho0, (size_t)2 * N * 8, hipMemcpyHostToDevice, s));
+        if (u0) HIPCHECK(c, hipMemcpyAsync(d_u, u0, (size_t)3 * N * 8, hipMemcpyHostToDevice, s));
         dispatch(c, [&](auto l) { decltype(l)::feq_state(c, d_rho, d_u, d_f); });
         dispatch(c, [&](auto l) { decltype(l)::scatter(c, d_f); });
         HIPCHECK(c, hipGetLastError());
@@ -581,9 +746,51 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n)
 {
     if (!c || n < 0) return fail(c, LBM_EINVAL, "bad arguments to lbm_step");
     if (c->unstable) return fail(c, LBM_ESTATE, "context flagged unstable");
+    const int64_t n0 = n;
+    const int G = c->graph_steps;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHECK(c, hipStreamIsCapturing(c->stream, &cs));
+    // inside the caller's own capture the kernels go straight into it
+    if (G > 0 && cs == hipStreamCaptureStatusNone) {
+        while (n >= G) {
+            hipGraphExec_t &gx = c->gx[c->cur];
+            if (!gx) {
+                if (!c->cap) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+                hipStream_t user = c->stream;
+                const int cur = c->cur;
+                c->stream = c->cap;
+                hipGraph_t graph = nullptr;
+                hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    for (int t = 0; t < G; t++) dispatch(c, [&](auto l) { decltype(l)::step(c); });
+                    e = hipStreamEndCapture(c->cap, &graph);
+                }
+                c->stream = user;
+                c->cur = cur;
+                if (e == hipSuccess) e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+                if (graph) (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("step graph: ") + hipGetErrorString(e));
+            }
+            HIPCHECK(c, hipGraphLaunch(gx, c->stream));
+            if (G % 2) c->cur ^= 1;
+            n -= G;
+        }
+    }
     for (int64_t t = 0; t < n; t++) dispatch(c, [&](auto l) { decltype(l)::step(c); });
     HIPCHECK(c, hipGetLastError());
-    c->steps += n;
+    c->steps += n0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_graph_steps(lbm_ctx *c, int steps_per_graph)
+{
+    if (!c || steps_per_graph < 0 || steps_per_graph > 4096) return fail(c, LBM_EINVAL, "bad steps per graph");
+    for (auto &g : c->gx)
+        if (g) {
+            HIPCHECK(c, hipGraphExecDestroy(g));
+            g = nullptr;
+        }
+    c->graph_steps = steps_per_graph;
     return LBM_OK;
 }
 
@@ -698,5 +905,374 @@ int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
 void lbm_destroy(lbm_ctx *c) { delete c; }
 
 const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+struct lbm_batch {
+    std::vector<lbm_ctx *> m;
+    int dim = 0, storage = 0, cfg = 0;
+    BatchTab tab{};
+    unsigned g_psi = 0, g_main = 0, g_chi = 0, g_out = 0, g_inl = 0, g_fill = 0;
+    hipStream_t stream = nullptr;
+    int cur = 0;
+    int64_t steps = 0;
+    std::string err;
+    int graph_steps = 16;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gx[2] = {nullptr, nullptr};
+    ~lbm_batch()
+    {
+        for (auto &g : gx)
+            if (g) (void)hipGraphExecDestroy(g);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (auto *c : m) delete c;
+    }
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+lbm_status bfail(lbm_batch *b, lbm_status st, const std::string &msg)
+{
+    if (b) b->err = msg;
+    else g_batch_error = msg;
+    return st;
+}
+
+#define BHIPCHECK(b, call)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return bfail(b, LBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+// Member configurations as the batch builds them: the batch's node-update
+// configuration everywhere.  Returns the per-member workspace sizes (0 = invalid).
+std::string batch_plan(const lbm_config *cfgs, int n, std::vector<lbm_config> &mc, std::vector<size_t> &bytes,
+                       size_t &tables, size_t &total)
+{
+    if (!cfgs || n < 1 || n > (1 << 20)) return "bad member count";
+    mc.assign(cfgs, cfgs + n);
+    bytes.assign(n, 0);
+    const int cfg = cfgs[0].tile_config;
+    total = 0;
+    for (int i = 0; i < n; i++) {
+        if (mc[i].dim != mc[0].dim || mc[i].storage != mc[0].storage)
+            return "batch members must share the lattice and the storage";
+        mc[i].tile_config = cfg;
+        bytes[i] = lbm_workspace_bytes(&mc[i]);
+        if (!bytes[i]) {
+            Canon k;
+            std::string why = canonicalize(&mc[i], k);
+            Maps m;
+            if (why.empty()) why = build_maps(&k.c, m);
+            return "member " + std::to_string(i) + ": " + why;
+        }
+        total += align_up(bytes[i]);
+    }
+    tables = align_up(sizeof(Member) * n) + 5 * align_up(sizeof(int) * (n + 1));
+    total += tables;
+    return "";
+}
+
+void batch_launch(lbm_batch *b, hipStream_t s)
+{
+    BatchArgs a{};
+    a.t = b->tab;
+    a.cur = b->cur;
+    a.g_psi = b->g_psi;
+    a.g_main = b->g_main;
+    a.g_chi = b->g_chi;
+    a.g_out = b->g_out;
+    a.g_inl = b->g_inl;
+    a.g_fill = b->g_fill;
+    a.stream = s;
+    if (b->dim == 2) Launcher<2>::batch_step(b->storage, b->cfg, a);
+    else Launcher<3>::batch_step(b->storage, b->cfg, a);
+    b->cur ^= 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(const lbm_config *cfgs, int n)
+{
+    std::vector<lbm_config> mc;
+    std::vector<size_t> bytes;
+    size_t tables = 0, total = 0;
+    if (!batch_plan(cfgs, n, mc, bytes, tables, total).empty()) return 0;
+    return total;
+}
+
+lbm_status lbm_batch_create(const lbm_config *cfgs, int n, void *dev_ws, size_t ws_bytes, void *hip_stream,
+                            lbm_batch **out)
+{
+    if (!out) return bfail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::vector<lbm_config> mc;
+    std::vector<size_t> bytes;
+    size_t tables = 0, total = 0;
+    const std::string why = batch_plan(cfgs, n, mc, bytes, tables, total);
+    if (!why.empty()) return bfail(nullptr, LBM_EINVAL, why);
+    if (!dev_ws) return bfail(nullptr, LBM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)dev_ws) % ALIGN) return bfail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < total) return bfail(nullptr, LBM_ENOMEM, "workspace too small");
+    lbm_batch *b = new lbm_batch();
+    b->stream = (hipStream_t)hip_stream;
+    b->dim = mc[0].dim;
+    b->storage = mc[0].storage;
+    char *ws = (char *)dev_ws;
+    size_t off = 0;
+    std::vector<Member> mem(n);
+    std::vector<int> item0(n + 1, 0), psi0(n + 1, 0), out0(n + 1, 0), inl0(n + 1, 0), fill0(n + 1, 0);
+    bool faces = false;
+    for (int i = 0; i < n; i++) {
+        lbm_ctx *c = nullptr;
+        const lbm_status st = lbm_create(&mc[i], ws + off, bytes[i], hip_stream, &c);
+        if (st != LBM_OK) {
+            const std::string msg = "member " + std::to_string(i) + ": " + g_create_error;
+            delete b;
+            return bfail(nullptr, st, msg);
+        }
+        b->m.push_back(c);
+        off += align_up(bytes[i]);
+        const Layout &L = c->L;
+        b->cfg = L.cfg;
+        Member &M = mem[i];
+        M.f[0] = c->ws + L.o_fA;
+        M.f[1] = c->ws + L.o_fB;
+        M.type = c->type();
+        M.psi = c->ws + L.o_psi;
+        M.g = L.g;
+        M.ph = c->ph;
+        M.bd = c->bd;
+        M.tiles_x = L.tiles[0];
+        M.tiles_y = L.tiles[1];
+        M.n_items = (int)L.nblocks_main;
+        M.item_list = (const int *)(c->ws + L.o_items);
+        M.nb_in = L.nb_in;
+        M.nb_out = L.nb_out;
+        M.flag = c->flag();
+        const bool chi_stage = L.boundary && c->bd.has_outlet && c->bd.chi_on;
+        item0[i + 1] = item0[i] + M.n_items;
+        psi0[i + 1] = psi0[i] + (L.psi_mode ? (int)((L.g.N + 255) / 256) : 0);
+        out0[i + 1] = out0[i] + (chi_stage ? L.nb_out : 0);
+        inl0[i + 1] = inl0[i] + (L.boundary ? L.nb_in + L.nb_out : 0);
+        fill0[i + 1] = fill0[i] + (L.boundary ? L.nb_out : 0);
+        faces = faces || L.boundary;
+    }
+    char *t = ws + off;
+    auto put = [&](const void *src, size_t nbytes) -> char * {
+        char *at = t;
+        t += align_up(nbytes);
+        return hipMemcpyAsync(at, src, nbytes, hipMemcpyHostToDevice, b->stream) == hipSuccess ? at : nullptr;
+    };
+    b->tab.n = n;
+    b->tab.m = (const Member *)put(mem.data(), sizeof(Member) * n);
+    b->tab.item0 = (const int *)put(item0.data(), sizeof(int) * (n + 1));
+    b->tab.psi0 = (const int *)put(psi0.data(), sizeof(int) * (n + 1));
+    b->tab.out0 = (const int *)put(out0.data(), sizeof(int) * (n + 1));
+    b->tab.inl0 = (const int *)put(inl0.data(), sizeof(int) * (n + 1));
+    b->tab.fill0 = (const int *)put(fill0.data(), sizeof(int) * (n + 1));
+    if (!b->tab.m || !b->tab.item0 || !b->tab.psi0 || !b->tab.out0 || !b->tab.inl0 || !b->tab.fill0) {
+        delete b;
+        return bfail(nullptr, LBM_EDEVICE, "upload of the batch tables failed");
+    }
+    if (hipStreamSynchronize(b->stream) != hipSuccess) {
+        delete b;
+        return bfail(nullptr, LBM_EDEVICE, "batch set-up failed");
+    }
+    // launch sizes: the node update is persistent, at most two blocks per
+    // resident slot (256 CUs x 4 blocks), a multiple of the 8 XCDs
+    const int items = item0[n];
+    b->g_main = (unsigned)std::min((items + 7) / 8 * 8, 2048);
+    b->g_psi = (unsigned)psi0[n];
+    b->g_chi = faces ? (unsigned)n : 0u;
+    b->g_out = (unsigned)out0[n];
+    b->g_inl = (unsigned)inl0[n];
+    b->g_fill = (unsigned)fill0[n];
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n)
+{
+    if (!b || n < 0) return bfail(b, LBM_EINVAL, "bad arguments to lbm_batch_step");
+    for (auto *c : b->m) {
+        if (c->unstable) return bfail(b, LBM_ESTATE, "a member is flagged unstable");
+        if (c->cur != b->cur) return bfail(b, LBM_ESTATE, "a member was stepped on its own; parities differ");
+    }
+    const int64_t n0 = n;
+    const int G = b->graph_steps;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    BHIPCHECK(b, hipStreamIsCapturing(b->stream, &cs));
+    if (G > 0 && cs == hipStreamCaptureStatusNone) {
+        while (n >= G) {
+            hipGraphExec_t &gx = b->gx[b->cur];
+            if (!gx) {
+                if (!b->cap) BHIPCHECK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+                const int cur = b->cur;
+                hipGraph_t graph = nullptr;
+                hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    for (int t = 0; t < G; t++) batch_launch(b, b->cap);
+                    e = hipStreamEndCapture(b->cap, &graph);
+                }
+                b->cur = cur;
+                if (e == hipSuccess) e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+                if (graph) (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+            }
+            BHIPCHECK(b, hipGraphLaunch(gx, b->stream));
+            if (G % 2) b->cur ^= 1;
+            n -= G;
+        }
+    }
+    for (int64_t t = 0; t < n; t++) batch_launch(b, b->stream);
+    BHIPCHECK(b, hipGetLastError());
+    b->steps += n0;
+    for (auto *c : b->m) {
+        c->cur = b->cur;
+        c->steps += n0;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_graph_steps(lbm_batch *b, int steps_per_graph)
+{
+    if (!b || steps_per_graph < 0 || steps_per_graph > 4096) return bfail(b, LBM_EINVAL, "bad steps per graph");
+    for (auto &g : b->gx)
+        if (g) {
+            BHIPCHECK(b, hipGraphExecDestroy(g));
+            g = nullptr;
+        }
+    b->graph_steps = steps_per_graph;
+    return LBM_OK;
+}
+
+int lbm_batch_size(const lbm_batch *b) { return b ? (int)b->m.size() : 0; }
+
+lbm_ctx *lbm_batch_member(lbm_batch *b, int i)
+{
+    if (!b || i < 0 || i >= (int)b->m.size()) return nullptr;
+    return b->m[i];
+}
+
+void lbm_batch_destroy(lbm_batch *b) { delete b; }
+
+const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Droplet labels
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// caller-frame box -> memory-frame box; empty string if valid
+std::string to_box(const lbm_ctx *c, const lbm_box *in, Box3 &bx)
+{
+    if (!in) return "box is NULL";
+    const Geometry &g = c->L.g;
+    for (int a = 0; a < 3; a++) {
+        const int ca = g.ax[a];
+        bx.lo[a] = in->lo[ca];
+        bx.hi[a] = in->hi[ca];
+        if (bx.lo[a] < 0 || bx.hi[a] > g.n[a] || bx.lo[a] > bx.hi[a]) return "box outside the domain";
+    }
+    return "";
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_probe(lbm_ctx *c, int k, const lbm_box *box, double threshold, int64_t *dev_count)
+{
+    if (!c || (k != 0 && k != 1) || !dev_count) return fail(c, LBM_EINVAL, "bad arguments to lbm_probe");
+    Box3 bx{};
+    const std::string why = to_box(c, box, bx);
+    if (!why.empty()) return fail(c, LBM_EINVAL, why);
+    const StepArgs a = step_args(c);
+    auto *out = (unsigned long long *)dev_count;
+    if (c->L.dim == 2) Launcher<2>::probe(c->L.storage, a, k, bx, (float)threshold, out);
+    else Launcher<3>::probe(c->L.storage, a, k, bx, (float)threshold, out);
+    HIPCHECK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_components(lbm_ctx *c, int k, const lbm_box *box, double threshold, lbm_component *out, int max_out,
+                          int *n_out)
+{
+    if (!c || (k != 0 && k != 1) || !n_out || max_out < 0 || (max_out > 0 && !out))
+        return fail(c, LBM_EINVAL, "bad arguments to lbm_components");
+    Box3 bx{};
+    const std::string why = to_box(c, box, bx);
+    if (!why.empty()) return fail(c, LBM_EINVAL, why);
+    const StepArgs a = step_args(c);
+    const int64_t N = c->L.g.N;
+    int *lab = nullptr, *slot = nullptr, *flags = nullptr;
+    CompStat *st = nullptr;
+    auto release = [&]() {
+        if (lab) (void)hipFree(lab);
+        if (slot) (void)hipFree(slot);
+        if (flags) (void)hipFree(flags);
+        if (st) (void)hipFree(st);
+    };
+    auto run = [&]() -> lbm_status {
+        HIPCHECK(c, hipMalloc(&lab, (size_t)N * 4));
+        HIPCHECK(c, hipMalloc(&slot, (size_t)N * 4));
+        HIPCHECK(c, hipMalloc(&flags, 8));
+        const bool d2 = c->L.dim == 2;
+        if (d2) Launcher<2>::lab_init(c->L.storage, a, k, bx, (float)threshold, lab);
+        else Launcher<3>::lab_init(c->L.storage, a, k, bx, (float)threshold, lab);
+        // propagate until no label changes (at most N rounds; pointer jumping
+        // makes it a few dozen in practice)
+        for (int64_t round = 0;; round++) {
+            if (round > N) return fail(c, LBM_EDEVICE, "label propagation did not converge");
+            HIPCHECK(c, hipMemsetAsync(flags, 0, 4, c->stream));
+            if (d2) Launcher<2>::lab_prop(a, lab, flags, 4);
+            else Launcher<3>::lab_prop(a, lab, flags, 4);
+            int changed = 0;
+            HIPCHECK(c, hipMemcpyAsync(&changed, flags, 4, hipMemcpyDeviceToHost, c->stream));
+            HIPCHECK(c, hipStreamSynchronize(c->stream));
+            if (!changed) break;
+        }
+        HIPCHECK(c, hipMemsetAsync(flags + 1, 0, 4, c->stream));
+        if (d2) Launcher<2>::lab_roots(a, lab, slot, flags + 1);
+        else Launcher<3>::lab_roots(a, lab, slot, flags + 1);
+        int nr = 0;
+        HIPCHECK(c, hipMemcpyAsync(&nr, flags + 1, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        *n_out = nr;
+        if (nr == 0) return LBM_OK;
+        HIPCHECK(c, hipMalloc(&st, sizeof(CompStat) * nr));
+        if (d2) Launcher<2>::lab_stats(a, lab, slot, st, nr);
+        else Launcher<3>::lab_stats(a, lab, slot, st, nr);
+        std::vector<CompStat> h(nr);
+        HIPCHECK(c, hipMemcpyAsync(h.data(), st, sizeof(CompStat) * nr, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        std::sort(h.begin(), h.end(), [](const CompStat &p, const CompStat &q) { return p.first < q.first; });
+        for (int i = 0; i < nr && i < max_out; i++) {
+            out[i].first = (int64_t)h[i].first;
+            out[i].size = (int64_t)h[i].size;
+            for (int d = 0; d < 3; d++) {
+                out[i].lo[d] = h[i].lo[d];
+                out[i].hi[d] = h[i].hi[d];
+            }
+        }
+        return LBM_OK;
+    };
+    const lbm_status r = run();
+    release();
+    return r;
+}
 
 }  // extern "C"

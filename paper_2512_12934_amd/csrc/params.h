@@ -42,17 +42,24 @@ struct Physics {
     int adhesion;
 };
 
-// Elements of padding before x = 0 in every row of a population plane: one
-// ghost slot is needed; 32 keeps x = 0 on a 128-byte boundary for FP32.
-constexpr int XOFF = 32;
-
+// Rows of a population plane are padded to whole 128-byte lines and x = 0
+// starts a line, so the unit-stride loads of a wave cover whole lines.
 struct Geometry {
     int n[3];
-    int P[3];              // padded sizes: rows of XOFF + n + 1 rounded up to 32
-                           // elements, n + 2 on the other lattice axes
+    int P[3];              // padded sizes: rows of xoff + n + 1 rounded up to a
+                           // whole number of lines, n + 2 on the other lattice axes
+    int xoff;              // elements before x = 0 in every row
     int periodic[3];
     int64_t N;             // box nodes
     int64_t Ppad;          // padded nodes (stride between population planes)
+    // The caller's frame: memory axis a holds the caller's lattice axis ax[a]
+    // (the axis normal to the open faces of a 3-D domain is put last, so face
+    // nodes are contiguous in memory).  ostride[a] is the caller-frame linear
+    // stride of memory axis a and dmap[i] the caller-frame index of memory
+    // direction i; used only where state enters or leaves the context.
+    int ax[3];
+    int64_t ostride[3];
+    signed char dmap[19];
 };
 
 struct Patch {
@@ -71,6 +78,8 @@ struct Boundary {
     const InletRec *in;
     const OutletRec *out;
     const int *bslot;         // [N] face-buffer slot of role nodes, -1 elsewhere
+    int n_xp;                 // fluid x_{N-1} nodes; face slots [0, n_in) are the inlet nodes and
+                              // [n_in, n_in + n_xp) the x_{N-1} nodes, both in record order
     float *faceF;             // [slots][2][3] force of this step at role nodes
     float *faceU;             // [slots] normal velocity at x' (outward)
     double *faceQ;            // [slots] rho u.n at inlet and x' nodes (eq. 23 terms)
@@ -79,8 +88,50 @@ struct Boundary {
     double *scal;             // device scalars, see SC_* below
 };
 
-// Node-update kernel modes: a time step, or moments output only.
-enum { MODE_STEP = 0, MODE_MOMENTS = 1 };
+// Threads per block of the face kernels (one wave: the face node counts are
+// small, so narrow blocks spread the uncoalesced face gathers over more CUs).
+constexpr int FACE_NT = 64;
+// Threads of the single block that forms the eq. 23 sums.
+constexpr int CHI_NT = 1024;
+
+// One member of a batch: what a single context passes to its step kernels.
+struct Member {
+    void *f[2];                // population arrays A and B
+    const uint32_t *type;
+    void *psi;                 // float2 per box node
+    Geometry g;
+    Physics ph;
+    Boundary bd;
+    int tiles_x, tiles_y, n_items;
+    const int *item_list;      // [n_items] tiles of the node update that hold fluid
+    int nb_in, nb_out;         // face-kernel blocks
+    int *flag;
+};
+
+// Device tables of a batch.  Every *0 array holds n + 1 prefix sums of the
+// per-member block (or work-item) counts of one launch, so a block finds its
+// member by a binary search and its local block index by a subtraction.
+struct BatchTab {
+    const Member *m;
+    int n;
+    const int *item0;          // node-update work items
+    const int *psi0;           // k_psi blocks
+    const int *out0;           // outlet-collision blocks
+    const int *inl0;           // inlet-kernel blocks (inlet nodes, then U_c partials)
+    const int *fill0;          // outlet-fill blocks
+};
+
+// An axis-aligned box of nodes [lo, hi) in the memory frame.
+struct Box3 {
+    int lo[3], hi[3];
+};
+
+// Aggregates of one connected component (caller frame).
+struct CompStat {
+    unsigned long long size;
+    unsigned long long first;  // smallest node index
+    int lo[3], hi[3];          // bounding box [lo, hi)
+};
 
 enum { SC_QIN = 0, SC_QOUT = 1, SC_CHI = 2, SC_UC = 3, SC_CLAMPS = 4, SC_COUNT = 8 };
 

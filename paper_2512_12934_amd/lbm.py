@@ -41,8 +41,24 @@ class Config(C.Structure):
                 ("nu", C.c_double * 2), ("s_q", C.c_double), ("s_eps_policy", C.c_int),
                 ("G12", C.c_double), ("Gw", C.c_double * 2), ("Fb", C.c_double * 3),
                 ("n_inlets", C.c_int), ("inlets", Inlet * MAX_INLETS), ("has_outlet", C.c_int),
-                ("outlet", Outlet), ("tile_config", C.c_int),
+                ("outlet", Outlet), ("tile_config", C.c_int), ("layout", C.c_int),
                 ("solid", C.c_void_p), ("rho0", C.c_void_p), ("u0", C.c_void_p)]
+
+
+class Box(C.Structure):
+    _fields_ = [("lo", C.c_int * 3), ("hi", C.c_int * 3)]
+
+
+class Component(C.Structure):
+    _fields_ = [("first", C.c_int64), ("size", C.c_int64), ("lo", C.c_int * 3), ("hi", C.c_int * 3)]
+
+
+def make_box(lo, hi):
+    b = Box()
+    for a in range(3):
+        b.lo[a] = int(lo[a]) if a < len(lo) else 0
+        b.hi[a] = int(hi[a]) if a < len(hi) else 1
+    return b
 
 
 class Flux(C.Structure):
@@ -80,22 +96,46 @@ def lib():
         L.lbm_time_kernels.restype = C.c_int
         L.lbm_tile_configs.argtypes = [C.c_int]
         L.lbm_tile_configs.restype = C.c_int
+        L.lbm_set_graph_steps.argtypes = [vp, C.c_int]
         L.lbm_steps_done.argtypes = [vp]
         L.lbm_steps_done.restype = C.c_int64
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = C.c_char_p
-        for name in ("lbm_create", "lbm_step", "lbm_moments", "lbm_mass_flux", "lbm_get_state", "lbm_set_state"):
+        L.lbm_probe.argtypes = [vp, C.c_int, C.POINTER(Box), C.c_double, vp]
+        L.lbm_probe.restype = C.c_int
+        L.lbm_components.argtypes = [vp, C.c_int, C.POINTER(Box), C.c_double, C.POINTER(Component), C.c_int,
+                                     C.POINTER(C.c_int)]
+        L.lbm_components.restype = C.c_int
+        L.lbm_batch_workspace_bytes.argtypes = [cp, C.c_int]
+        L.lbm_batch_workspace_bytes.restype = C.c_size_t
+        L.lbm_batch_create.argtypes = [cp, C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbm_batch_step.argtypes = [vp, C.c_int64]
+        L.lbm_batch_set_graph_steps.argtypes = [vp, C.c_int]
+        L.lbm_batch_size.argtypes = [vp]
+        L.lbm_batch_size.restype = C.c_int
+        L.lbm_batch_member.argtypes = [vp, C.c_int]
+        L.lbm_batch_member.restype = vp
+        L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_batch_destroy.restype = None
+        L.lbm_batch_last_error.argtypes = [vp]
+        L.lbm_batch_last_error.restype = C.c_char_p
+        for name in ("lbm_create", "lbm_step", "lbm_moments", "lbm_mass_flux", "lbm_get_state", "lbm_set_state",
+                     "lbm_batch_create", "lbm_batch_step", "lbm_batch_set_graph_steps", "lbm_set_graph_steps"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
 
 
-def make_config(case, storage="f32", tile_config=-1):
+LAYOUT = {"caller": 0, "face_last": 1}
+
+
+def make_config(case, storage="f32", tile_config=-1, layout="caller"):
     """Fill an ``lbm_config`` from a case; returns (config, arrays kept alive)."""
     cfg = Config()
     cfg.tile_config = int(tile_config)
+    cfg.layout = LAYOUT[layout]
     cfg.dim = case.dim
     cfg.storage = STORE[storage]
     for a in range(3):
@@ -148,15 +188,15 @@ def resolve_tile_config(case, storage, tile_config):
     return int(tile_config)
 
 
-def workspace_bytes(case, storage="f32", tile_config=-1):
-    cfg, keep = make_config(case, storage, tile_config)
+def workspace_bytes(case, storage="f32", tile_config=-1, layout="caller"):
+    cfg, keep = make_config(case, storage, tile_config, layout)
     return int(lib().lbm_workspace_bytes(C.byref(cfg)))
 
 
 class LBM:
     """One simulation context on a GPU (device memory from torch)."""
 
-    def __init__(self, case, storage="f32", device="cuda:0", stream=None, tile_config=-1):
+    def __init__(self, case, storage="f32", device="cuda:0", stream=None, tile_config=-1, layout="caller"):
         import torch
         L = lib()
         self.case = case
@@ -165,7 +205,7 @@ class LBM:
         self.N = int(np.prod(case.n))
         self.device = torch.device(device)
         self.tile_config = resolve_tile_config(case, storage, tile_config)
-        cfg, keep = make_config(case, storage, self.tile_config)
+        cfg, keep = make_config(case, storage, self.tile_config, layout)
         nbytes = int(L.lbm_workspace_bytes(C.byref(cfg)))
         if nbytes == 0:
             h = C.c_void_p()
@@ -198,6 +238,10 @@ class LBM:
 
     def step(self, n=1):
         self._check(lib().lbm_step(self._h, int(n)))
+
+    def set_graph_steps(self, k):
+        """Steps per replayed HIP graph in step() (0: plain launches)."""
+        self._check(lib().lbm_set_graph_steps(self._h, int(k)))
 
     def moments(self, check=True):
         """Return (rho [2,N], u [3,N]) as float64 numpy arrays."""
@@ -240,3 +284,100 @@ class LBM:
     @property
     def steps(self):
         return int(lib().lbm_steps_done(self._h))
+
+    def probe(self, k, lo, hi, threshold, out):
+        """Enqueue the count of component-k nodes above threshold in the box
+        [lo, hi) into ``out`` (an int64 CUDA tensor element, e.g. series[i:i+1])."""
+        box = make_box(lo, hi)
+        self._check(lib().lbm_probe(self._h, int(k), C.byref(box), float(threshold), C.c_void_p(out.data_ptr())))
+
+    def components(self, k, lo, hi, threshold, max_out=4096):
+        """Face-connected components of {rho_k > threshold} in the box:
+        list of dicts (first node, size, bbox lo/hi), by first node."""
+        box = make_box(lo, hi)
+        out = (Component * max_out)()
+        n = C.c_int(0)
+        self._check(lib().lbm_components(self._h, int(k), C.byref(box), float(threshold), out, int(max_out),
+                                         C.byref(n)))
+        return [{"first": out[i].first, "size": out[i].size, "lo": tuple(out[i].lo), "hi": tuple(out[i].hi)}
+                for i in range(min(n.value, max_out))], n.value
+
+
+class _Member(LBM):
+    """A batch member seen as a context (owned by its batch)."""
+
+    def __init__(self, batch, i, case):
+        self.case = case
+        self.dim = case.dim
+        self.Q = 9 if case.dim == 2 else 19
+        self.N = int(np.prod(case.n))
+        self.device = batch.device
+        self.stream = batch.stream
+        self.tile_config = batch.tile_config
+        self._batch = batch              # keeps the workspace alive
+        self._h = C.c_void_p(lib().lbm_batch_member(batch._h, int(i)))
+
+    def close(self):
+        self._h = None                   # the batch owns the member
+
+
+class Batch:
+    """Many contexts stepped together (one launch per stage for all members)."""
+
+    def __init__(self, case_list, storage="f32", device="cuda:0", stream=None, tile_config=-1):
+        import torch
+        L = lib()
+        self.cases = list(case_list)
+        n = len(self.cases)
+        self.device = torch.device(device)
+        self.tile_config = resolve_tile_config(self.cases[0], storage, tile_config) if n else -1
+        cfgs = (Config * n)()
+        self._keep = []
+        for i, c in enumerate(self.cases):
+            cfg, keep = make_config(c, storage, self.tile_config)
+            cfgs[i] = cfg
+            self._keep.append(keep)
+        nbytes = int(L.lbm_batch_workspace_bytes(cfgs, n))
+        if nbytes == 0:
+            h = C.c_void_p()
+            st = L.lbm_batch_create(cfgs, n, None, 0, None, C.byref(h))
+            raise LBMError(st, L.lbm_batch_last_error(None).decode())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        st = L.lbm_batch_create(cfgs, n, C.c_void_p(self.ws.data_ptr()), nbytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != LBM_OK:
+            raise LBMError(st, L.lbm_batch_last_error(None).decode())
+        self._h = h
+        self.workspace_bytes = nbytes
+        self.members = [_Member(self, i, c) for i, c in enumerate(self.cases)]
+
+    def _check(self, st):
+        if st != LBM_OK:
+            raise LBMError(st, lib().lbm_batch_last_error(self._h).decode())
+
+    def step(self, n=1):
+        self._check(lib().lbm_batch_step(self._h, int(n)))
+
+    def set_graph_steps(self, k):
+        self._check(lib().lbm_batch_set_graph_steps(self._h, int(k)))
+
+    def __len__(self):
+        return len(self.members)
+
+    def __getitem__(self, i):
+        return self.members[i]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for m in self.members:
+                m._h = None
+            lib().lbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:lbm_status|size_t|void|int64_t|const char \*)\s*\*?\s*(lbm_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:lbm_status|size_t|void|int64_t|int|lbm_ctx|const char)\s*\*?\s*((?:lbm|surr)_\w+)\s*\(",
                                  src, re.M)))
 
 
@@ -57,3 +57,29 @@ def test_create_rejects_invalid_config_before_any_device_work(lib):
     assert st == lbm.LBM_EINVAL
     assert b"viscosities" in lib.lbm_last_error(None)
     assert lib.lbm_step(None, 1) == lbm.LBM_EINVAL
+
+
+def test_batch_workspace_validates(lib):
+    from paper_2512_12934_amd import cases, lbm
+    a = cases.tjunction(W=20, length=90, x_side=30, side_width=14, side_len=18)
+    b = cases.tjunction(W=24, length=120, x_side=36, side_width=24, side_len=24)
+    n = 2
+    cfgs = (lbm.Config * n)()
+    keep = []
+    for i, c in enumerate((a, b)):
+        cfg, k = lbm.make_config(c)
+        cfgs[i] = cfg
+        keep.append(k)
+    total = lib.lbm_batch_workspace_bytes(cfgs, n)
+    assert total >= lbm.workspace_bytes(a) + lbm.workspace_bytes(b)
+    # members must share the lattice
+    c3 = cases.coflow3d(length=12, width=5, inner=2)
+    cfg3, k3 = lbm.make_config(c3)
+    cfgs[1] = cfg3
+    assert lib.lbm_batch_workspace_bytes(cfgs, n) == 0
+    h = C.c_void_p()
+    assert lib.lbm_batch_create(cfgs, n, None, 0, None, C.byref(h)) == lbm.LBM_EINVAL
+    assert b"share" in lib.lbm_batch_last_error(None)
+    assert lib.lbm_batch_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_size(None) == 0
+    assert lib.lbm_batch_member(None, 0) is None

@@ -1,0 +1,81 @@
+"""Surrogate kernels against the FP64 oracle: gradients of the hand-written
+backward pass, one Adam update, BF16 matrix-core inference with the ensemble
+statistics, determinism, and that training fits a smooth map."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as mo
+
+pytestmark = pytest.mark.gpu
+
+H = 128
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, (n, 4)).astype(np.float32)
+    Y = np.stack([np.sin(2 * X[:, 0]) + 0.5 * X[:, 1] * X[:, 2], np.cos(X[:, 3]) - 0.3 * X[:, 0]], 1)
+    return X, Y.astype(np.float32)
+
+
+def test_gradients_match_oracle():
+    from paper_2512_12934_amd.surrogate import Surrogate
+    s = Surrogate(members=3, max_n=512, seed=7)
+    X, Y = _data(300, 1)                  # five tiles, the last one ragged
+    g, l = s.forward_backward(X, Y)
+    th = s.get_params().astype(np.float64)
+    for m in range(3):
+        go = mo.grad(th[m], X, Y, H)
+        lo = mo.loss(th[m], X, Y, H)
+        err = np.abs(g[m] - go).max() / np.abs(go).max()
+        print(f"  member {m}: grad rel err {err:.2e}, loss {l[m]:.6f} vs {lo:.6f}", flush=True)
+        assert err < 1e-4
+        assert abs(l[m] - lo) < 1e-5 * max(1.0, lo)
+
+
+def test_adam_step_matches_oracle():
+    from paper_2512_12934_amd.surrogate import Surrogate
+    s = Surrogate(members=2, max_n=256, seed=3)
+    X, Y = _data(200, 2)
+    th0 = s.get_params().astype(np.float64)
+    s.train(X, Y, epochs=2, lr=1e-2)
+    th = s.get_params().astype(np.float64)
+    for m in range(2):
+        t, mm, vv = th0[m], np.zeros(th0.shape[1]), np.zeros(th0.shape[1])
+        for k in (1, 2):
+            t, mm, vv = mo.adam(t, mm, vv, mo.grad(t, X, Y, H), k, lr=1e-2)
+        err = np.abs(th[m] - t).max()
+        print(f"  member {m}: max |param - oracle| after 2 steps {err:.2e}", flush=True)
+        assert err < 2e-5
+
+
+def test_bf16_inference_and_ensemble_match_oracle():
+    import torch
+    from paper_2512_12934_amd.surrogate import Surrogate
+    s = Surrogate(members=5, max_n=1024, seed=11)
+    X, Y = _data(1000, 3)
+    s.train(X, Y, epochs=20, lr=3e-3)
+    th = s.get_params().astype(np.float64)
+    Xq, _ = _data(777, 4)
+    mean, sd, fb = s.predict(Xq, threshold=0.05)
+    torch.cuda.synchronize()
+    mu, so, fo = mo.ensemble(list(th), Xq, H, 0.05)
+    em = np.abs(mean.cpu().numpy() - mu).max()
+    es = np.abs(sd.cpu().numpy() - so).max()
+    print(f"  mean err {em:.2e}, std err {es:.2e}", flush=True)
+    assert em < 2e-3 and es < 2e-3
+    # flags agree wherever the decision is not within rounding of the threshold
+    margin = np.abs(so - 0.05 * np.abs(mu)).min(axis=1) > 5e-3
+    assert (fb.cpu().numpy()[margin].astype(bool) == fo[margin]).all()
+
+
+def test_training_is_deterministic_and_fits():
+    from paper_2512_12934_amd.surrogate import Surrogate
+    X, Y = _data(2048, 5)
+    a = Surrogate(members=2, max_n=2048, seed=1)
+    b = Surrogate(members=2, max_n=2048, seed=1)
+    la = a.train(X, Y, epochs=1500, lr=3e-3)
+    lb = b.train(X, Y, epochs=1500, lr=3e-3)
+    assert np.array_equal(a.get_params(), b.get_params())
+    print(f"  loss after 1500 epochs {la}", flush=True)
+    assert (la < 2e-3).all()
