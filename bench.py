@@ -22,6 +22,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (2-comp MRT) + %HBM peak; batched/surrogate vs plain at stated error"
+# rocprofv3 summary of the node update on this workload (HBM bytes per launch
+# from FETCH_SIZE and WRITE_SIZE, scaled by the calibration kernel)
+PROFILE = os.path.join(ROOT, "profiles", "k_main_coflow3d_600x120x120_f32.md")
+KERNEL_SOURCES = ["kernels.h", "lattice.h", "params.h", "launch.h", "launch_impl.h", "k3d.hip"]
+
+
+def sources_sha():
+    """Digest of the sources the node update is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_12934_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the node update as profiled, or None when the
+    profile is missing or was taken from other kernel sources."""
+    import re
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_per_launch: fetch_bytes=(\d+) write_bytes=(\d+) sources_sha256=([0-9a-f]+)", text)
+    if not m or m.group(3) != sources_sha():
+        return None
+    return int(m.group(1)) + int(m.group(2))
 HBM_PEAK_GBS = 8000.0
 
 
@@ -36,10 +64,52 @@ def parse():
     ap.add_argument("--inner", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle baseline (0 disables it)")
-    ap.add_argument("--no-extra", action="store_true", help="skip the secondary FP16 and 2-D measurements")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary FP16, 2-D and batched measurements")
+    ap.add_argument("--batch-members", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=400)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale reference for HBM counters)")
     return ap.parse_args()
+
+
+def batched(args, dev, t0, t1):
+    """The 256-instance T-junction sweep (W 32..128, FP16-offset storage):
+    one batch (one launch per stage for all members, graph-replayed) against
+    the same members stepped one context at a time."""
+    import torch
+    from paper_2512_12934_amd import cases
+    from paper_2512_12934_amd.lbm import Batch, lib
+    cs = cases.sweep(args.batch_members)
+    fluid = sum(c.fluid_nodes for c in cs)
+    tc = time.perf_counter()
+    b = Batch(cs, storage="f16", device=dev)
+    t_create = time.perf_counter() - tc
+    b.step(32)
+    torch.cuda.synchronize()
+    nb = args.batch_steps
+    t0.record(b.stream)
+    b.step(nb)
+    t1.record(b.stream)
+    torch.cuda.synchronize()
+    mb = t0.elapsed_time(t1) / nb
+    # the same members, one context at a time (plain launches, as a caller
+    # without the batch would run them)
+    L = lib()
+    ns = max(4, nb // 16)
+    for m in b.members:
+        m.set_graph_steps(0)
+    t0.record(b.stream)
+    for m in b.members:
+        L.lbm_step(m._h, ns)
+    t1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / ns
+    del b
+    torch.cuda.empty_cache()
+    return {"members": len(cs), "fluid_nodes": fluid, "storage": "f16",
+            "batched_ms_per_step": round(mb, 4), "batched_MLUPS": round(fluid / (mb / 1e3) / 1e6, 1),
+            "one_by_one_ms_per_step": round(ms, 4), "one_by_one_MLUPS": round(fluid / (ms / 1e3) / 1e6, 1),
+            "speedup": round(ms / mb, 2), "create_s": round(t_create, 2)}
 
 
 def main():
@@ -97,7 +167,8 @@ def main():
     flux = sim.mass_flux()
     finite = bool(np.isfinite(flux["mass"]).all())
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": profiled_traffic() if args.storage == "f32" and args.length == 600 else None,
             "kernel": "k_main<3,%d>" % (0 if args.storage == "f32" else 1),
             "kernel_ms": round(kms[0], 5), "bytes_per_node": b_main, "nodes_per_launch": fluid,
             "mode": "two-pass (k_psi + k_main)" if two_pass else "fused (k_main only)",
@@ -132,6 +203,8 @@ def main():
         extra["tjunction_800x100_d2q9_f32"] = {"ms_per_step": round(m3, 4),
                                                "MLUPS": round(tj.fluid_nodes / (m3 / 1e3) / 1e6, 1)}
         del s3
+        torch.cuda.empty_cache()
+        extra["batched_sweep"] = batched(args, dev, t0, t1)
 
     cpu = None
     if args.cpu_seconds > 0:

@@ -58,6 +58,28 @@ class Case:
         return c
 
 
+# Adhesion strength that makes the dispersed phase non-wetting (contact angle
+# ~180 degrees) at G12 = 0.9: from oracle sessile-drop runs on a 100 x 50
+# channel (drop of radius 15, 6000 steps), the contact angle grows from ~85
+# degrees at 0 to ~159 at 0.08 and the drop lifts off the wall at 0.1.
+# tests/test_oracle_physics.py repeats the two end points.
+GW_NONWETTING = 0.1
+
+
+def sessile(g: float, nx: int = 100, ny: int = 50, R: float = 15.0, major: float = 1.0,
+            minor: float = 0.03) -> Case:
+    """Half-disc droplet of component 1 resting on the lower of two walls,
+    periodic along x, adhesion +g (component 1) and -g (component 2)."""
+    c = Case("sessile", 2, (nx, ny, 1), (True, False, True), (1.0 / 6.0, 1.0 / 6.0), 0.9,
+             solid=None, rho0=None, Gw=(g, -g))
+    x, y, _ = c.grid()
+    c.solid = ((y == 0) | (y == ny - 1)).astype(np.uint8)
+    inside = ((x - nx / 2) ** 2 + (y - 1) ** 2 < R * R) & (y >= 1)
+    c.rho0 = _rho_from_mask(inside, major, minor)
+    c.meta.update(R=R, major=major, minor=minor)
+    return c
+
+
 def _rho_from_mask(inside: np.ndarray, major: float, minor: float) -> np.ndarray:
     """Component 1 is ``major`` where ``inside``; component 2 is mirrored."""
     rho = np.empty((2, inside.size))
@@ -261,7 +283,7 @@ def channel(length: int, width: int, u_in: float, nu=(0.067, 0.067), G12: float 
 
 def tjunction(W: int = 100, length: int = 800, x_side: int = 150, side_width: int = 100,
               side_len: int = 100, u_c: float = 0.01, u_d: float = 0.005,
-              nu=(0.067, 0.067), G12: float = 0.9, Gw_mag: float = 0.0,
+              nu=(0.067, 0.067), G12: float = 0.9, Gw_mag: float = None,
               major: float = 1.0, minor: float = 0.03, alpha_on=True, chi_on=True) -> Case:
     """Main channel ``length`` x ``W`` fluid nodes between solid rows y = 0 and
     y = W+1, side channel of width ``side_width`` over x in
@@ -270,7 +292,10 @@ def tjunction(W: int = 100, length: int = 800, x_side: int = 150, side_width: in
     dispersed phase (component 1) enters through the top of the side channel
     with u_d (downwards); convective outlet at x = length-1.  Walls repel the
     dispersed phase with adhesion +Gw_mag and attract the continuous phase
-    with -Gw_mag."""
+    with -Gw_mag (default GW_NONWETTING: the dispersed phase does not wet the
+    walls)."""
+    if Gw_mag is None:
+        Gw_mag = GW_NONWETTING
     nx = length
     ny = W + 2 + side_len
     c = Case("tjunction", 2, (nx, ny, 1), (False, False, False), tuple(nu), G12,

@@ -38,10 +38,13 @@ namespace lbm {
 // storage codecs: FP32, or binary16 of (f - w_i) with round-to-nearest-even
 // ---------------------------------------------------------------------------
 template <int STORE> struct Codec;
+// Both storages hold f_i - w_i (the population less its rest-state value
+// at unit density): the stored numbers are small where a component is the
+// majority phase, so storage rounding is small too.
 template <> struct Codec<0> {
     using T = float;
-    static __device__ __forceinline__ float ld(const T *p, float) { return *p; }
-    static __device__ __forceinline__ void st(T *p, float v, float) { *p = v; }
+    static __device__ __forceinline__ float ld(const T *p, float w) { return *p + w; }
+    static __device__ __forceinline__ void st(T *p, float v, float w) { *p = v - w; }
 };
 template <> struct Codec<1> {
     using T = __half;
@@ -57,13 +60,13 @@ constexpr int BUF_FLAGS = 0x00020000;   // dword 3 of a raw gfx9 buffer descript
 template <int STORE> struct Buf;
 template <> struct Buf<0> {
     static constexpr uint32_t SZ = 4;
-    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float)
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w)
     {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, so, 0));
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, so, 0)) + w;
     }
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float)
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v - w), r, (int)vo, so, 0);
     }
 };
 template <> struct Buf<1> {
@@ -159,10 +162,41 @@ __device__ __forceinline__ void bgather(__amdgpu_buffer_rsrc_t rs, const Geometr
 {
     constexpr uint32_t SZ = Buf<STORE>::SZ;
     if (wave_fast) {
-        const uint32_t vo = p * SZ;
+        // lane offset of x - 1 with the (y, z) part of the shift applied, so
+        // the x part is a small non-negative immediate, and the plane of
+        // direction i as the wave-uniform offset (the same plane offsets as
+        // the stores use, which keeps the uniform state small)
+        const uint32_t vb = (p - 1u) * SZ;
+        const uint32_t sy = (uint32_t)g.P[0] * SZ, sz = (uint32_t)g.P[0] * (uint32_t)g.P[1] * SZ;
         static_for<Lat<DIM>::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            f[i] = Buf<STORE>::ld(rs, vo, (int)(((int64_t)i * g.Ppad - dir_off<DIM>(g, i)) * SZ), weight<DIM>(i));
+            constexpr int ex = Lat<DIM>::E[i][0], ey = Lat<DIM>::E[i][1], ez = Lat<DIM>::E[i][2];
+            uint32_t vo = vb + (uint32_t)(1 - ex) * SZ;
+            if constexpr (ey == 1) vo -= sy;
+            if constexpr (ey == -1) vo += sy;
+            if constexpr (ez == 1) vo -= sz;
+            if constexpr (ez == -1) vo += sz;
+            f[i] = Buf<STORE>::ld(rs, vo, (int)((int64_t)i * g.Ppad * SZ), weight<DIM>(i));
+        });
+    } else if (__ballot(tw & T_EDGE) == 0) {
+        // walls but no periodic wrap in this wave: per lane either the
+        // streamed slot or the node's own slot of the opposite direction
+        // (bounce-back), selected without branches; the plane goes into the
+        // lane offset so the wave-uniform offset is zero
+        const uint32_t vb = (p - 1u) * SZ;
+        const uint32_t sy = (uint32_t)g.P[0] * SZ, sz = (uint32_t)g.P[0] * (uint32_t)g.P[1] * SZ;
+        const uint32_t plane = (uint32_t)g.Ppad * SZ;
+        static_for<Lat<DIM>::Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int ex = Lat<DIM>::E[i][0], ey = Lat<DIM>::E[i][1], ez = Lat<DIM>::E[i][2];
+            uint32_t vo = vb + (uint32_t)(1 - ex) * SZ;
+            if constexpr (ey == 1) vo -= sy;
+            if constexpr (ey == -1) vo += sy;
+            if constexpr (ez == 1) vo -= sz;
+            if constexpr (ez == -1) vo += sz;
+            const uint32_t own = p * SZ + (uint32_t)Lat<DIM>::OPP[i] * plane;
+            const uint32_t a = ((tw >> i) & 1u) ? own : vo + (uint32_t)i * plane;
+            f[i] = Buf<STORE>::ld(rs, a, 0, weight<DIM>(i));
         });
     } else {
         static_for<Lat<DIM>::Q>([&](auto ic) {
@@ -558,21 +592,25 @@ __global__ __launch_bounds__(256) void k_psi(const typename Codec<STORE>::T *__r
     psi_body<DIM, STORE>((int)blockIdx.x, src, type, g, psi);
 }
 
-// Density and momentum of the populations of one component.
+// Density and momentum of the populations of one component.  The momentum is
+// summed over opposite pairs, f_i - f_opp(i) first: the two are close, so
+// their difference is exact and the small differences add with little
+// rounding (the velocity is a small difference of large populations).
 template <int DIM>
 __device__ __forceinline__ void moments_of(const float (&f)[Lat<DIM>::Q], float &rho, float (&J)[3])
 {
     rho = 0.0f;
-    J[0] = J[1] = J[2] = 0.0f;
-    static_for<Lat<DIM>::Q>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        rho += f[i];
-        static_for<3>([&](auto dc) {
-            constexpr int d = decltype(dc)::value;
+    static_for<Lat<DIM>::Q>([&](auto ic) { rho += f[decltype(ic)::value]; });
+    static_for<3>([&](auto dc) {
+        constexpr int d = decltype(dc)::value;
+        float acc = 0.0f;
+        static_for<Pairs<DIM>::P>([&](auto pc) {
+            constexpr int i = Pairs<DIM>::first(decltype(pc)::value);
             constexpr int e = Lat<DIM>::E[i][d];
-            if constexpr (e == 1) J[d] += f[i];
-            else if constexpr (e == -1) J[d] -= f[i];
+            if constexpr (e == 1) acc += f[i] - f[Lat<DIM>::OPP[i]];
+            else if constexpr (e == -1) acc -= f[i] - f[Lat<DIM>::OPP[i]];
         });
+        J[d] = acc;
     });
 }
 
@@ -600,26 +638,41 @@ __global__ __launch_bounds__(256) void k_moments(const typename Codec<STORE>::T 
         out_u[bo] = out_u[g.N + bo] = out_u[2 * g.N + bo] = 0.0;
         return;
     }
+    auto psi_at = [&](int dx, int dy, int dz) {
+        const int qx = map_axis(x + dx, g.n[0], g.periodic[0]);
+        const int qy = map_axis(y + dy, g.n[1], g.periodic[1]);
+        const int qz = DIM == 3 ? map_axis(z + dz, g.n[2], g.periodic[2]) : 0;
+        return psi[(int64_t)qx + (int64_t)g.n[0] * ((int64_t)qy + (int64_t)g.n[1] * qz)];
+    };
+    // the stencil in pairs of opposite offsets, in the node update's order
+    // (sweep distance, then lateral offsets), so u matches the step's
     float g1[3] = {0.f, 0.f, 0.f}, g2[3] = {0.f, 0.f, 0.f}, A[3] = {0.f, 0.f, 0.f};
-    static_for<(DIM == 3 ? 125 : 25)>([&](auto oc) {
-        constexpr int o = decltype(oc)::value;
-        constexpr int dx = o % 5 - 2, dy = (o / 5) % 5 - 2, dz = DIM == 3 ? o / 25 - 2 : 0;
-        constexpr int r2 = dx * dx + dy * dy + dz * dz;
-        constexpr float w = stencil_w<DIM>(r2);
-        if constexpr (r2 != 0 && w != 0.0f) {
-            const int qx = map_axis(x + dx, g.n[0], g.periodic[0]);
-            const int qy = map_axis(y + dy, g.n[1], g.periodic[1]);
-            const int qz = DIM == 3 ? map_axis(z + dz, g.n[2], g.periodic[2]) : 0;
-            const float2 v = psi[(int64_t)qx + (int64_t)g.n[0] * ((int64_t)qy + (int64_t)g.n[1] * qz)];
-            const float sv = signbit(v.x) ? 1.0f : 0.0f;
-            const int e3[3] = {dx, dy, dz};
-            static_for<3>([&](auto dc) {
-                constexpr int d = decltype(dc)::value;
-                g1[d] = fmaf(w * e3[d], v.x, g1[d]);
-                g2[d] = fmaf(w * e3[d], v.y, g2[d]);
-                A[d] = fmaf(w * e3[d], sv, A[d]);
-            });
-        }
+    static_for<3>([&](auto sdc) {
+        constexpr int SD = decltype(sdc)::value;
+        static_for<25>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            constexpr int a = o % 5 - 2, bq = o / 5 - 2;
+            constexpr int dx = a, dy = DIM == 3 ? bq : SD, dz = DIM == 3 ? SD : 0;
+            constexpr int lat_y = DIM == 3 ? bq : 0;
+            constexpr int r2 = dx * dx + dy * dy + dz * dz;
+            constexpr float w = stencil_w<DIM>(r2);
+            constexpr bool half = SD > 0 || (lat_y > 0 || (lat_y == 0 && dx > 0));
+            constexpr bool in2d = DIM == 3 || bq == 0;
+            if constexpr (half && in2d && w != 0.0f) {
+                const float2 vp = psi_at(dx, dy, dz), vm = psi_at(-dx, -dy, -dz);
+                const float d1 = vp.x - vm.x, d2 = vp.y - vm.y;
+                const float ds = (signbit(vp.x) ? 1.0f : 0.0f) - (signbit(vm.x) ? 1.0f : 0.0f);
+                const int e3[3] = {dx, dy, dz};
+                static_for<3>([&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    if (e3[d] != 0) {
+                        g1[d] = fmaf(w * e3[d], d1, g1[d]);
+                        g2[d] = fmaf(w * e3[d], d2, g2[d]);
+                        A[d] = fmaf(w * e3[d], ds, A[d]);
+                    }
+                });
+            }
+        });
     });
     if (!ph.adhesion) A[0] = A[1] = A[2] = 0.0f;
     const float2 ps = psi[b];

@@ -37,7 +37,7 @@ class Scaler:
         return np.asarray(a, np.float64) * self.sd + self.mu
 
 
-def generate(params, steps, every=100, storage="f16", chunk=256, device="cuda:0", log=print):
+def generate(params, steps, every=100, storage="f32", chunk=256, device="cuda:0", log=print):
     """Run every instance of ``params`` (list of (W, Ca, q, M)) for ``steps``
     steps, batched ``chunk`` at a time; returns (labels, seconds): labels[i]
     is a dict with D_over_W, T_star (None where undefined) and the series."""
@@ -96,3 +96,57 @@ def evaluate(sur, xs, ys, X_raw, Y_true, threshold=0.05):
     return {"mape_all": ape.mean(0).tolist(),
             "mape_kept": ape[keep].mean(0).tolist() if keep.any() else None,
             "fallback_rate": float(fb.mean()), "seconds_per_query": dt / len(Xn), "n": int(len(Xn))}
+
+
+def run(n_train, n_test, steps, W_range, every=100, members=5, epochs=3000, lr=3e-3, threshold=0.05,
+        seed_train=12935, seed_test=12936, log=print):
+    """Label n_train + n_test batched runs, train the ensemble on the usable
+    training labels, and judge it on the held-out ones."""
+    from .surrogate import Surrogate
+    p_tr = cases.sweep_params(n_train, seed_train, W_range)
+    p_te = cases.sweep_params(n_test, seed_test, W_range)
+    lab_tr, t_tr = generate(p_tr, steps, every, log=log)
+    lab_te, t_te = generate(p_te, steps, every, log=log)
+    keep_tr = [i for i, l in enumerate(lab_tr) if usable(l)]
+    keep_te = [i for i, l in enumerate(lab_te) if usable(l)]
+    out = {"train_runs": n_train, "test_runs": n_test, "steps": steps, "W_range": list(W_range),
+           "usable_train": len(keep_tr), "usable_test": len(keep_te),
+           "lbm_seconds_per_run": (t_tr + t_te) / (n_train + n_test)}
+    if len(keep_tr) < 8 or not keep_te:
+        out["note"] = "too few labelled runs"
+        return out
+    Xtr = features([p_tr[i] for i in keep_tr])
+    Ytr = np.array([[lab_tr[i]["D_over_W"], lab_tr[i]["T_star"]] for i in keep_tr])
+    Xte = features([p_te[i] for i in keep_te])
+    Yte = np.array([[lab_te[i]["D_over_W"], lab_te[i]["T_star"]] for i in keep_te])
+    xs, ys = Scaler(Xtr), Scaler(Ytr)
+    sur = Surrogate(members=members, max_n=max(len(Xtr), 64), seed=0)
+    loss = sur.train(xs.fwd(Xtr).astype(np.float32), ys.fwd(Ytr).astype(np.float32), epochs, lr)
+    out["train_loss"] = loss.tolist()
+    out["held_out"] = evaluate(sur, xs, ys, Xte, Yte, threshold)
+    out["gain_seconds_per_query"] = out["lbm_seconds_per_run"] / out["held_out"]["seconds_per_query"]
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="label batched T-junction runs, train and judge the surrogate")
+    ap.add_argument("--train", type=int, default=512)
+    ap.add_argument("--test", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=100000)
+    ap.add_argument("--wmin", type=int, default=16)
+    ap.add_argument("--wmax", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=3000)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    res = run(a.train, a.test, a.steps, (a.wmin, a.wmax), epochs=a.epochs)
+    s = json.dumps(res)
+    print(s, flush=True)
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(s + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,100 @@
+"""FP32 and FP16-offset storage against the FP64 oracle on the Laplace case
+(64 x 64 periodic, droplet R = 16): fields at step 1000, the droplet's
+equivalent diameter, and the surface tension from the Laplace fit over
+R = 10 .. 20.
+
+FP32 storage holds the fields to 1e-4 relative (L2 norm) at step 1000.  FP16 storage
+of f - w_i holds the diameter and the surface tension to a few percent, not
+to the 1% the extension aims at: the offset w_i suits a component near unit
+density, but each component is also present at the minority density 0.03
+(0.1 in the Laplace sweep), where f - w_i is close to -w_i and the 11-bit
+significand leaves a relative error near 1% on every such population
+(test_fp16_offset_meets_one_percent records that bar as an expected
+failure)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2512_12934_amd import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _dp_reff(rho, c):
+    p = (rho[0] + rho[1]) / 3 + c.G12 * rho[0] * rho[1]
+    thr = 0.5 * (rho[0].max() + rho[0].min())
+    Reff = np.sqrt((rho[0] > thr).sum() / np.pi)
+    n = c.n[0]
+    return p[n // 2 + n * (n // 2)] - p[0], Reff
+
+
+def _gamma(pts):
+    pts = np.array(pts)
+    x, y = 1 / pts[:, 1], pts[:, 0]
+    A = np.vstack([x, np.ones_like(x)]).T
+    (g, _), *_ = np.linalg.lstsq(A, y, rcond=None)
+    return g
+
+
+_cache = {}
+
+
+def _errors():
+    """Field, diameter and surface-tension errors of both storages (once)."""
+    if _cache:
+        return _cache
+    from paper_2512_12934_amd.lbm import LBM
+    c = cases.laplace()
+    s = oracle.Sim(c)
+    s.step(1000)
+    ro, uo, _ = s.moments()
+    for storage in ("f32", "f16"):
+        g = LBM(c, storage=storage)
+        g.step(1000)
+        rg, ug = g.moments()
+        er = np.abs(rg - ro).max() / np.abs(ro).max()
+        eu = np.abs(ug - uo).max() / np.abs(uo).max()
+        er2 = np.linalg.norm(rg - ro) / np.linalg.norm(ro)
+        eu2 = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+        _, Rg = _dp_reff(rg, c)
+        _, Ro = _dp_reff(ro, c)
+        _cache[storage] = {"rho": er, "u": eu, "rho_l2": er2, "u_l2": eu2, "D": abs(Rg - Ro) / Ro}
+    pts = {"oracle": [], "f32": [], "f16": []}
+    for R in (10, 12, 14, 16, 18, 20):
+        c = cases.laplace(R=R, major=0.93, minor=0.1)
+        s = oracle.Sim(c)
+        s.step(2000)
+        pts["oracle"].append(_dp_reff(s.moments()[0], c))
+        for storage in ("f32", "f16"):
+            g = LBM(c, storage=storage)
+            g.step(2000)
+            pts[storage].append(_dp_reff(g.moments()[0], c))
+    gam = {k: _gamma(v) for k, v in pts.items()}
+    for storage in ("f32", "f16"):
+        _cache[storage]["gamma"] = abs(gam[storage] - gam["oracle"]) / gam["oracle"]
+    for storage in ("f32", "f16"):
+        e = _cache[storage]
+        print(f"  {storage}: max-norm rho {e['rho']:.2e} u {e['u']:.2e}; L2 rho {e['rho_l2']:.2e} u {e['u_l2']:.2e}; "
+              f"diameter {e['D']:.2e}  gamma {e['gamma']:.2e}", flush=True)
+    return _cache
+
+
+def test_fp32_fields_diameter_and_surface_tension():
+    """Relative errors in the L2 norm over the box below 1e-4; the largest
+    single-node velocity error, relative to the largest velocity (a spurious
+    current of ~1e-3, so FP32 rounding of ~1e-7 sits near 1e-4), below 2e-4."""
+    e = _errors()["f32"]
+    assert e["rho_l2"] < 1e-4 and e["u_l2"] < 1e-4
+    assert e["rho"] < 1e-4 and e["u"] < 2e-4
+    assert e["D"] < 1e-3 and e["gamma"] < 1e-3
+
+
+def test_fp16_offset_within_a_few_percent():
+    e = _errors()["f16"]
+    assert e["D"] < 0.05 and e["gamma"] < 0.08
+
+
+@pytest.mark.xfail(strict=True, reason="f - w_i in binary16 loses ~1% per population at the minority density")
+def test_fp16_offset_meets_one_percent():
+    e = _errors()["f16"]
+    assert e["D"] < 0.01 and e["gamma"] < 0.01

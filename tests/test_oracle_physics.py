@@ -211,7 +211,7 @@ def test_alpha_inlet_recovers_prescribed_momentum(alpha_on):
     interaction force here, so the half-force term vanishes).  The original
     extrapolation of eq. (13) alone does not."""
     c = cases.tjunction(W=20, length=80, x_side=30, side_width=12, side_len=16,
-                        G12=0.0, alpha_on=alpha_on)
+                        G12=0.0, Gw_mag=0.0, alpha_on=alpha_on)
     s = oracle.Sim(c)
     s.step(60)
     f = s.get_f()
@@ -335,3 +335,23 @@ def test_rotated_device_gives_rotated_fields(axes):
     da, db = a.diag(), b.diag()
     for key in ("q_in", "q_out", "chi", "u_conv"):
         assert abs(da[key] - db[key]) < 1e-12, key
+
+
+def _contact_angle(c, steps):
+    s = oracle.Sim(c)
+    s.step(steps)
+    rho, _, _ = s.moments()
+    nx, ny = c.n[0], c.n[1]
+    m = rho[0].reshape(ny, nx) > 0.5 * (1.0 + 0.03)
+    base = int(m[1].sum())
+    ys = np.nonzero(m[1:-1])[0] + 1
+    h = ys.max() - 0.5
+    return 180.0 if base == 0 else float(np.degrees(2 * np.arctan2(2 * h, base)))
+
+
+def test_adhesion_contact_angle():
+    """Eq. 11 with constant strengths: no adhesion gives a neutral contact
+    angle near 90 degrees; the calibrated non-wetting strength lifts the
+    dispersed drop off the wall (contact angle 180 degrees)."""
+    assert 75.0 < _contact_angle(cases.sessile(0.0), 6000) < 105.0
+    assert _contact_angle(cases.sessile(cases.GW_NONWETTING), 6000) == 180.0
