@@ -35,21 +35,29 @@
 namespace lbm {
 
 // ---------------------------------------------------------------------------
-// storage codecs: FP32, or binary16 of (f - w_i) with round-to-nearest-even
+// Storage codecs.  A population is stored less an offset:
+//   FP32:     f_i - w_i                         (the rest state at unit density)
+//   binary16: f_i - w_i r, rounded to nearest even, where r is the previous
+//             step's density of the component at the node that reads the
+//             slot (the reference density, the same at write and at read).
+// Near local equilibrium the stored numbers are then small for both the
+// majority and the minority phase, so an 11-bit significand keeps the
+// relative error of every population small; a fixed offset w_i would leave
+// about 1% at a minority density of 0.03.  ld / st take the weight w and the
+// reference density r of the reading node (FP32 ignores r).
 // ---------------------------------------------------------------------------
 template <int STORE> struct Codec;
-// Both storages hold f_i - w_i (the population less its rest-state value
-// at unit density): the stored numbers are small where a component is the
-// majority phase, so storage rounding is small too.
 template <> struct Codec<0> {
     using T = float;
-    static __device__ __forceinline__ float ld(const T *p, float w) { return *p + w; }
-    static __device__ __forceinline__ void st(T *p, float v, float w) { *p = v - w; }
+    static constexpr bool REF = false;
+    static __device__ __forceinline__ float ld(const T *p, float w, float) { return *p + w; }
+    static __device__ __forceinline__ void st(T *p, float v, float w, float) { *p = v - w; }
 };
 template <> struct Codec<1> {
     using T = __half;
-    static __device__ __forceinline__ float ld(const T *p, float w) { return __half2float(*p) + w; }
-    static __device__ __forceinline__ void st(T *p, float v, float w) { *p = __float2half_rn(v - w); }
+    static constexpr bool REF = true;
+    static __device__ __forceinline__ float ld(const T *p, float w, float r) { return __half2float(*p) + w * r; }
+    static __device__ __forceinline__ void st(T *p, float v, float w, float r) { *p = __float2half_rn(v - w * r); }
 };
 
 // Raw buffer access for the node update: one descriptor per component array
@@ -60,25 +68,27 @@ constexpr int BUF_FLAGS = 0x00020000;   // dword 3 of a raw gfx9 buffer descript
 template <int STORE> struct Buf;
 template <> struct Buf<0> {
     static constexpr uint32_t SZ = 4;
-    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w)
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w, float)
     {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, so, 0)) + w;
     }
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w)
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w,
+                                              float)
     {
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v - w), r, (int)vo, so, 0);
     }
 };
 template <> struct Buf<1> {
     static constexpr uint32_t SZ = 2;
-    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w)
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w, float rr)
     {
         const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, so, 0);
-        return __half2float(__ushort_as_half(h)) + w;
+        return __half2float(__ushort_as_half(h)) + w * rr;
     }
-    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w)
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w,
+                                              float rr)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v - w)), r, (int)vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v - w * rr)), r, (int)vo, so, 0);
     }
 };
 
@@ -134,22 +144,23 @@ __device__ __forceinline__ int64_t slot_of(const Geometry &g, int64_t p, uint32_
 }
 
 // Post-streaming populations of one component at one node (pointer access).
+// rr: the node's reference density of this component (see Codec).
 template <int DIM, int STORE>
 __device__ __forceinline__ void gather(const typename Codec<STORE>::T *__restrict__ fk, const Geometry &g,
                                        int64_t p, uint32_t tw, int x, int y, int z,
-                                       float (&f)[Lat<DIM>::Q])
+                                       float (&f)[Lat<DIM>::Q], float rr)
 {
     static_for<Lat<DIM>::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        f[i] = Codec<STORE>::ld(fk + slot_of<DIM>(g, p, tw, x, y, z, i), weight<DIM>(i));
+        f[i] = Codec<STORE>::ld(fk + slot_of<DIM>(g, p, tw, x, y, z, i), weight<DIM>(i), rr);
     });
 }
 
 template <int DIM, int STORE>
 __device__ __forceinline__ float gather1(const typename Codec<STORE>::T *__restrict__ fk, const Geometry &g,
-                                         int64_t p, uint32_t tw, int x, int y, int z, int i)
+                                         int64_t p, uint32_t tw, int x, int y, int z, int i, float rr)
 {
-    return Codec<STORE>::ld(fk + slot_of<DIM>(g, p, tw, x, y, z, i), weight<DIM>(i));
+    return Codec<STORE>::ld(fk + slot_of<DIM>(g, p, tw, x, y, z, i), weight<DIM>(i), rr);
 }
 
 // Buffer gather: for a wave whose nodes all stream in from in-box neighbours
@@ -158,7 +169,7 @@ __device__ __forceinline__ float gather1(const typename Codec<STORE>::T *__restr
 // wave-uniform.
 template <int DIM, int STORE>
 __device__ __forceinline__ void bgather(__amdgpu_buffer_rsrc_t rs, const Geometry &g, uint32_t p, uint32_t tw,
-                                        int x, int y, int z, bool wave_fast, float (&f)[Lat<DIM>::Q])
+                                        int x, int y, int z, bool wave_fast, float (&f)[Lat<DIM>::Q], float rr)
 {
     constexpr uint32_t SZ = Buf<STORE>::SZ;
     if (wave_fast) {
@@ -176,7 +187,7 @@ __device__ __forceinline__ void bgather(__amdgpu_buffer_rsrc_t rs, const Geometr
             if constexpr (ey == -1) vo += sy;
             if constexpr (ez == 1) vo -= sz;
             if constexpr (ez == -1) vo += sz;
-            f[i] = Buf<STORE>::ld(rs, vo, (int)((int64_t)i * g.Ppad * SZ), weight<DIM>(i));
+            f[i] = Buf<STORE>::ld(rs, vo, (int)((int64_t)i * g.Ppad * SZ), weight<DIM>(i), rr);
         });
     } else if (__ballot(tw & T_EDGE) == 0) {
         // walls but no periodic wrap in this wave: per lane either the
@@ -196,13 +207,13 @@ __device__ __forceinline__ void bgather(__amdgpu_buffer_rsrc_t rs, const Geometr
             if constexpr (ez == -1) vo += sz;
             const uint32_t own = p * SZ + (uint32_t)Lat<DIM>::OPP[i] * plane;
             const uint32_t a = ((tw >> i) & 1u) ? own : vo + (uint32_t)i * plane;
-            f[i] = Buf<STORE>::ld(rs, a, 0, weight<DIM>(i));
+            f[i] = Buf<STORE>::ld(rs, a, 0, weight<DIM>(i), rr);
         });
     } else {
         static_for<Lat<DIM>::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             const uint32_t a = (uint32_t)slot_of<DIM>(g, (int64_t)p, tw, x, y, z, i);
-            f[i] = Buf<STORE>::ld(rs, a * SZ, 0, weight<DIM>(i));
+            f[i] = Buf<STORE>::ld(rs, a * SZ, 0, weight<DIM>(i), rr);
         });
     }
 }
@@ -298,8 +309,9 @@ template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB
 __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__restrict__ src,
                                           typename Codec<STORE>::T *__restrict__ dst,
                                           const uint32_t *__restrict__ type, const float2 *__restrict__ psi,
-                                          const Geometry &g, const Physics &ph, const Boundary &bd, int tiles_x,
-                                          int tiles_y, int item, int *__restrict__ flag)
+                                          const float2 *__restrict__ ref, const Geometry &g, const Physics &ph,
+                                          const Boundary &bd, int tiles_x, int tiles_y, int item,
+                                          int *__restrict__ flag)
 {
     constexpr int Q = Lat<DIM>::Q;
     constexpr int LY = DIM == 3 ? TY : 1;          // lateral y extent of the tile
@@ -365,9 +377,11 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                 float p1 = 0.0f, p2 = 0.0f;
                 if (fluid) {
                     float f[Q];
-                    bgather<DIM, STORE>(rs0, g, pp, tw, gx, gy, gz, wave_fast, f);
+                    float2 rf = make_float2(0.0f, 0.0f);
+                    if constexpr (Codec<STORE>::REF) rf = ref[(int64_t)gx + (int64_t)g.n[0] * ((int64_t)gy + (int64_t)g.n[1] * gz)];
+                    bgather<DIM, STORE>(rs0, g, pp, tw, gx, gy, gz, wave_fast, f, rf.x);
                     static_for<Q>([&](auto ic) { p1 += f[decltype(ic)::value]; });
-                    bgather<DIM, STORE>(rs1, g, pp, tw, gx, gy, gz, wave_fast, f);
+                    bgather<DIM, STORE>(rs1, g, pp, tw, gx, gy, gz, wave_fast, f, rf.y);
                     static_for<Q>([&](auto ic) { p2 += f[decltype(ic)::value]; });
                 }
                 s_psi[slot] = make_float2(p1, p2);
@@ -406,6 +420,11 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                 });
                 constexpr int CEN = (DIM == 3 ? 2 * HX : 0) + 2;   // the node itself
                 const float2 ps = s_psi[base[2] + CEN];
+                // psi(t) of the node for the next step's reference densities
+                // and the face kernels (the two-pass mode has it from k_psi)
+                if constexpr (PSRC == 0) const_cast<float2 *>(psi)[b] = ps;
+                float2 rf = make_float2(0.0f, 0.0f);
+                if constexpr (Codec<STORE>::REF) rf = ref[b];
 
                 // ---- wall adhesion (eq. 11): only nodes with a solid within the stencil
                 float A[3] = {0.f, 0.f, 0.f};
@@ -474,10 +493,10 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                 float J1[3], J2[3];
                 {
                     float f[Q];
-                    bgather<DIM, STORE>(rs0, g, p, tw, x, y, z, wave_fast, f);
+                    bgather<DIM, STORE>(rs0, g, p, tw, x, y, z, wave_fast, f, rf.x);
                     to_pairs<DIM>(f, qa);
                     pair_momentum<DIM>(qa, J1);
-                    bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f);
+                    bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f, rf.y);
                     to_pairs<DIM>(f, qb);
                     pair_momentum<DIM>(qb, J2);
                 }
@@ -511,23 +530,36 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                 const __amdgpu_buffer_rsrc_t rd0 = comp_rsrc<STORE>(dst, 0, Q, g.Ppad);
                 const __amdgpu_buffer_rsrc_t rd1 = comp_rsrc<STORE>(dst, 1, Q, g.Ppad);
                 const uint32_t vo = p * Buf<STORE>::SZ;
+                // reference density of the node that reads population i next
+                // step: the destination x + e_i, or x itself on bounce-back
+                auto dest_psi = [&](auto ic) -> float2 {
+                    constexpr int i = decltype(ic)::value;
+                    constexpr int ex = Lat<DIM>::E[i][0], ey = Lat<DIM>::E[i][1], ez = Lat<DIM>::E[i][2];
+                    if ((tw >> Lat<DIM>::OPP[i]) & 1u) return ps;
+                    if constexpr (DIM == 3) return s_psi[base[2 + ez] + CEN + ey * HX + ex];
+                    else return s_psi[base[2 + ey] + CEN + ex];
+                };
                 float fo[Q];
                 const Rates ra = {ph.se[0], ph.seps[0], ph.sq, ph.snu[0]};
                 collide_pairs<DIM>(qa, r1, J1, u, F1, ra, fo);
                 static_for<Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
-                    Buf<STORE>::st(rd0, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i));
+                    float rd = 0.0f;
+                    if constexpr (Codec<STORE>::REF) rd = dest_psi(ic).x;
+                    Buf<STORE>::st(rd0, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i), rd);
                 });
                 if constexpr (!KEEPB) {
                     float f[Q];
-                    bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f);
+                    bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f, rf.y);
                     to_pairs<DIM>(f, qb);
                 }
                 const Rates rb = {ph.se[1], ph.seps[1], ph.sq, ph.snu[1]};
                 collide_pairs<DIM>(qb, r2, J2, u, F2, rb, fo);
                 static_for<Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
-                    Buf<STORE>::st(rd1, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i));
+                    float rd = 0.0f;
+                    if constexpr (Codec<STORE>::REF) rd = dest_psi(ic).y;
+                    Buf<STORE>::st(rd1, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i), rd);
                 });
             }
         }
@@ -540,15 +572,16 @@ template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB
 __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__restrict__ src,
                                               typename Codec<STORE>::T *__restrict__ dst,
                                               const uint32_t *__restrict__ type,
-                                              const float2 *__restrict__ psi, Geometry g, Physics ph,
-                                              Boundary bd, int tiles_x, int tiles_y, int n_items,
-                                              const int *__restrict__ item_list, int *__restrict__ flag)
+                                              const float2 *__restrict__ psi, const float2 *__restrict__ ref,
+                                              Geometry g, Physics ph, Boundary bd, int tiles_x, int tiles_y,
+                                              int n_items, const int *__restrict__ item_list,
+                                              int *__restrict__ flag)
 {
     // XCD-aware work item: blocks are dealt round-robin to the 8 XCDs
     const int per = (int)(gridDim.x + 7) / 8;
     const int k = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (k < n_items)
-        main_item<DIM, STORE, PSRC, TX, TY, W, ZC, KEEPB>(src, dst, type, psi, g, ph, bd, tiles_x, tiles_y,
+        main_item<DIM, STORE, PSRC, TX, TY, W, ZC, KEEPB>(src, dst, type, psi, ref, g, ph, bd, tiles_x, tiles_y,
                                                           item_list[k], flag);
 }
 
@@ -560,7 +593,7 @@ __global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__
 template <int DIM, int STORE>
 __device__ __forceinline__ void psi_body(int blk, const typename Codec<STORE>::T *__restrict__ src,
                                              const uint32_t *__restrict__ type, Geometry g,
-                                             float2 *__restrict__ psi)
+                                             float2 *__restrict__ psi, const float2 *__restrict__ ref)
 {
     constexpr int Q = Lat<DIM>::Q;
     const int64_t b = (int64_t)blk * 256 + threadIdx.x;
@@ -577,9 +610,11 @@ __device__ __forceinline__ void psi_body(int blk, const typename Codec<STORE>::T
     coords_of(g, b, x, y, z);
     const uint32_t p = (uint32_t)pidx(g, x, y, DIM == 3 ? z : -1);
     float f[Q], r1 = 0.0f, r2 = 0.0f;
-    bgather<DIM, STORE>(comp_rsrc<STORE>(src, 0, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f);
+    float2 rf = make_float2(0.0f, 0.0f);
+    if constexpr (Codec<STORE>::REF) rf = ref[b];
+    bgather<DIM, STORE>(comp_rsrc<STORE>(src, 0, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f, rf.x);
     static_for<Q>([&](auto ic) { r1 += f[decltype(ic)::value]; });
-    bgather<DIM, STORE>(comp_rsrc<STORE>(src, 1, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f);
+    bgather<DIM, STORE>(comp_rsrc<STORE>(src, 1, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f, rf.y);
     static_for<Q>([&](auto ic) { r2 += f[decltype(ic)::value]; });
     psi[b] = make_float2(r1, r2);
 }
@@ -587,9 +622,9 @@ __device__ __forceinline__ void psi_body(int blk, const typename Codec<STORE>::T
 template <int DIM, int STORE>
 __global__ __launch_bounds__(256) void k_psi(const typename Codec<STORE>::T *__restrict__ src,
                                              const uint32_t *__restrict__ type, Geometry g,
-                                             float2 *__restrict__ psi)
+                                             float2 *__restrict__ psi, const float2 *__restrict__ ref)
 {
-    psi_body<DIM, STORE>((int)blockIdx.x, src, type, g, psi);
+    psi_body<DIM, STORE>((int)blockIdx.x, src, type, g, psi, ref);
 }
 
 // Density and momentum of the populations of one component.  The momentum is
@@ -622,8 +657,9 @@ __device__ __forceinline__ void moments_of(const float (&f)[Lat<DIM>::Q], float 
 template <int DIM, int STORE>
 __global__ __launch_bounds__(256) void k_moments(const typename Codec<STORE>::T *__restrict__ src,
                                                  const uint32_t *__restrict__ type,
-                                                 const float2 *__restrict__ psi, Geometry g, Physics ph,
-                                                 double *__restrict__ out_rho, double *__restrict__ out_u)
+                                                 const float2 *__restrict__ psi, const float2 *__restrict__ ref,
+                                                 Geometry g, Physics ph, double *__restrict__ out_rho,
+                                                 double *__restrict__ out_u)
 {
     constexpr int Q = Lat<DIM>::Q;
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -679,9 +715,10 @@ __global__ __launch_bounds__(256) void k_moments(const typename Codec<STORE>::T 
     const float r1 = ps.x, r2 = ps.y, rt = r1 + r2;
     const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
     float f[Q], ra, rb, Ja[3], Jb[3];
-    gather<DIM, STORE>(src, g, p, tw | T_EDGE, x, y, z, f);
+    const float2 rf = ref[b];
+    gather<DIM, STORE>(src, g, p, tw | T_EDGE, x, y, z, f, rf.x);
     moments_of<DIM>(f, ra, Ja);
-    gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, f);
+    gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, f, rf.y);
     moments_of<DIM>(f, rb, Jb);
     out_rho[bo] = r1;
     out_rho[g.N + bo] = r2;
@@ -727,8 +764,9 @@ static __global__ __launch_bounds__(CHI_NT) void k_chi(Boundary bd) { chi_body(b
 template <int DIM, int STORE>
 __device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>::T *__restrict__ src,
                                                     typename Codec<STORE>::T *__restrict__ dst,
-                                                    const uint32_t *__restrict__ type, Geometry g, Physics ph,
-                                                    Boundary bd, int *__restrict__ flag)
+                                                    const uint32_t *__restrict__ type,
+                                                    const float2 *__restrict__ psi, const float2 *__restrict__ ref,
+                                                    Geometry g, Physics ph, Boundary bd, int *__restrict__ flag)
 {
     using T = typename Codec<STORE>::T;
     constexpr int Q = Lat<DIM>::Q;
@@ -741,8 +779,9 @@ __device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>
     const uint32_t tw = type[rec.bN];
     const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
     float fa[Q], fb[Q];
-    gather<DIM, STORE>(src, g, p, tw, x, y, z, fa);
-    gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw, x, y, z, fb);
+    const float2 rf = ref[rec.bN];
+    gather<DIM, STORE>(src, g, p, tw, x, y, z, fa, rf.x);
+    gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw, x, y, z, fb, rf.y);
     float r1, r2, J1[3], J2[3];
     moments_of<DIM>(fa, r1, J1);
     moments_of<DIM>(fb, r2, J2);
@@ -761,6 +800,16 @@ __device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>
         else u[2] = un;
     }
     if (!(rt > 0.0f) || !isfinite(rt) || !isfinite(u[0] + u[1] + u[2])) *flag = 1;
+    // reference density of the node that reads population i next step
+    auto dest_psi = [&](auto ic) -> float2 {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (!Codec<STORE>::REF) return make_float2(0.0f, 0.0f);
+        if ((tw >> Lat<DIM>::OPP[i]) & 1u) return psi[rec.bN];
+        const int qx = map_axis(x + Lat<DIM>::E[i][0], g.n[0], g.periodic[0]);
+        const int qy = map_axis(y + Lat<DIM>::E[i][1], g.n[1], g.periodic[1]);
+        const int qz = DIM == 3 ? map_axis(z + Lat<DIM>::E[i][2], g.n[2], g.periodic[2]) : 0;
+        return psi[(int64_t)qx + (int64_t)g.n[0] * ((int64_t)qy + (int64_t)g.n[1] * qz)];
+    };
     float fo[Q];
     PairF<DIM> q;
     to_pairs<DIM>(fa, q);
@@ -768,7 +817,7 @@ __device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>
     collide_pairs<DIM>(q, r1, J1, u, F1, s1, fo);
     static_for<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        Codec<STORE>::st(dst + (int64_t)i * g.Ppad + p, fo[i], weight<DIM>(i));
+        Codec<STORE>::st(dst + (int64_t)i * g.Ppad + p, fo[i], weight<DIM>(i), dest_psi(ic).x);
     });
     to_pairs<DIM>(fb, q);
     const Rates s2 = {ph.se[1], ph.seps[1], ph.sq, ph.snu[1]};
@@ -776,17 +825,18 @@ __device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>
     T *d2 = dst + (int64_t)Q * g.Ppad;
     static_for<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        Codec<STORE>::st(d2 + (int64_t)i * g.Ppad + p, fo[i], weight<DIM>(i));
+        Codec<STORE>::st(d2 + (int64_t)i * g.Ppad + p, fo[i], weight<DIM>(i), dest_psi(ic).y);
     });
 }
 
 template <int DIM, int STORE>
 __global__ __launch_bounds__(FACE_NT) void k_outlet(const typename Codec<STORE>::T *__restrict__ src,
                                                     typename Codec<STORE>::T *__restrict__ dst,
-                                                    const uint32_t *__restrict__ type, Geometry g, Physics ph,
-                                                    Boundary bd, int *__restrict__ flag)
+                                                    const uint32_t *__restrict__ type,
+                                                    const float2 *__restrict__ psi, const float2 *__restrict__ ref,
+                                                    Geometry g, Physics ph, Boundary bd, int *__restrict__ flag)
 {
-    outlet_body<DIM, STORE>((int)blockIdx.x, src, dst, type, g, ph, bd, flag);
+    outlet_body<DIM, STORE>((int)blockIdx.x, src, dst, type, psi, ref, g, ph, bd, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -795,7 +845,8 @@ __global__ __launch_bounds__(FACE_NT) void k_outlet(const typename Codec<STORE>:
 // ---------------------------------------------------------------------------
 template <int DIM, int STORE>
 __device__ __forceinline__ void inlet_body(int blk, typename Codec<STORE>::T *__restrict__ dst,
-                                                   const uint32_t *__restrict__ type, Geometry g, Boundary bd,
+                                                   const uint32_t *__restrict__ type,
+                                                   const float2 *__restrict__ psi, Geometry g, Boundary bd,
                                                    int nb_in)
 {
     using T = typename Codec<STORE>::T;
@@ -819,8 +870,10 @@ __device__ __forceinline__ void inlet_body(int blk, typename Codec<STORE>::T *__
         float fa2[Q], fb2[Q], ra2 = 0.f, rb2 = 0.f, u2[3] = {0.f, 0.f, 0.f};
         if (x2_fluid) {
             float Ja[3], Jb[3];
-            gather<DIM, STORE>(dst, g, p2, tw2, x2, y2, z2, fa2);
-            gather<DIM, STORE>(dst + (int64_t)Q * g.Ppad, g, p2, tw2, x2, y2, z2, fb2);
+            // f(t+1) is read with psi(t) as the reference density
+            const float2 r2f = psi[rec.b2];
+            gather<DIM, STORE>(dst, g, p2, tw2, x2, y2, z2, fa2, r2f.x);
+            gather<DIM, STORE>(dst + (int64_t)Q * g.Ppad, g, p2, tw2, x2, y2, z2, fb2, r2f.y);
             moments_of<DIM>(fa2, ra2, Ja);
             moments_of<DIM>(fb2, rb2, Jb);
             const float *F2 = bd.faceF + (int64_t)rec.slot2 * 6;
@@ -840,7 +893,9 @@ __device__ __forceinline__ void inlet_body(int blk, typename Codec<STORE>::T *__
             const float rho2 = k == 0 ? ra2 : rb2;
             const float(&f2)[Q] = k == 0 ? fa2 : fb2;
             float f1[Q];
-            gather<DIM, STORE>(dk, g, p1, tw1, x1, y1, z1, f1);
+            const float2 r1f = psi[rec.b1];
+            const float rref1 = k == 0 ? r1f.x : r1f.y;
+            gather<DIM, STORE>(dk, g, p1, tw1, x1, y1, z1, f1, rref1);
             // eq. (13)/(14) on the populations entering the domain
             static_for<Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
@@ -886,7 +941,7 @@ __device__ __forceinline__ void inlet_body(int blk, typename Codec<STORE>::T *__
                 constexpr int i = decltype(ic)::value;
                 if (e_axis<DIM>(i, pt.axis) * pt.sign > 0)
                     Codec<STORE>::st(dk + (int64_t)i * g.Ppad + src_slot<DIM>(g, x1, y1, z1, i), f1[i],
-                                     weight<DIM>(i));
+                                     weight<DIM>(i), rref1);
             });
         });
         return;
@@ -905,7 +960,8 @@ __device__ __forceinline__ void inlet_body(int blk, typename Codec<STORE>::T *__
             static_for<2>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 float f[Q], rk, Jk[3];
-                gather<DIM, STORE>(dst + (int64_t)k * Q * g.Ppad, g, p, tw, x, y, z, f);
+                const float2 rpf = psi[rec.bP];
+                gather<DIM, STORE>(dst + (int64_t)k * Q * g.Ppad, g, p, tw, x, y, z, f, k == 0 ? rpf.x : rpf.y);
                 moments_of<DIM>(f, rk, Jk);
                 rt += rk;
                 J += bd.out_sign * pick3(Jk, bd.out_axis);
@@ -926,10 +982,11 @@ __device__ __forceinline__ void inlet_body(int blk, typename Codec<STORE>::T *__
 
 template <int DIM, int STORE>
 __global__ __launch_bounds__(FACE_NT) void k_inlet(typename Codec<STORE>::T *__restrict__ dst,
-                                                   const uint32_t *__restrict__ type, Geometry g, Boundary bd,
+                                                   const uint32_t *__restrict__ type,
+                                                   const float2 *__restrict__ psi, Geometry g, Boundary bd,
                                                    int nb_in)
 {
-    inlet_body<DIM, STORE>((int)blockIdx.x, dst, type, g, bd, nb_in);
+    inlet_body<DIM, STORE>((int)blockIdx.x, dst, type, psi, g, bd, nb_in);
 }
 
 // ---------------------------------------------------------------------------
@@ -938,7 +995,9 @@ __global__ __launch_bounds__(FACE_NT) void k_inlet(typename Codec<STORE>::T *__r
 template <int DIM, int STORE>
 __device__ __forceinline__ void outlet_fill_body(int blk, const typename Codec<STORE>::T *__restrict__ src,
                                                          typename Codec<STORE>::T *__restrict__ dst,
-                                                         const uint32_t *__restrict__ type, Geometry g, Boundary bd)
+                                                         const uint32_t *__restrict__ type,
+                                                         const float2 *__restrict__ psi,
+                                                         const float2 *__restrict__ ref, Geometry g, Boundary bd)
 {
     using T = typename Codec<STORE>::T;
     constexpr int Q = Lat<DIM>::Q;
@@ -966,21 +1025,26 @@ __device__ __forceinline__ void outlet_fill_body(int blk, const typename Codec<S
         pp = pidx(g, xp, yp, DIM == 3 ? zp : -1);
     }
     const float uc = (float)Uc;
+    // the slot read by x_N: f(t) was stored with the reference density of
+    // step t, f(t+1) is stored with psi(t); x' is read at t+1 with psi(t)
+    const float2 rt0 = ref[rec.bN], rt1 = psi[rec.bN];
+    const float2 rp = rec.slotP >= 0 ? psi[rec.bP] : make_float2(0.0f, 0.0f);
     static_for<2>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         const T *sk = src + (int64_t)k * Q * g.Ppad;
         T *dk = dst + (int64_t)k * Q * g.Ppad;
+        const float r0 = k == 0 ? rt0.x : rt0.y, r1 = k == 0 ? rt1.x : rt1.y, rpk = k == 0 ? rp.x : rp.y;
         static_for<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if (e_axis<DIM>(i, bd.out_axis) * bd.out_sign < 0) {
                 const int64_t a = (int64_t)i * g.Ppad + src_slot<DIM>(g, x, y, z, i);
-                const float prev = Codec<STORE>::ld(sk + a, weight<DIM>(i));
+                const float prev = Codec<STORE>::ld(sk + a, weight<DIM>(i), r0);
                 float v = prev;
                 if (rec.slotP >= 0) {
-                    const float fp = gather1<DIM, STORE>(dk, g, pp, twp, xp, yp, zp, i);
+                    const float fp = gather1<DIM, STORE>(dk, g, pp, twp, xp, yp, zp, i, rpk);
                     v = (prev + uc * fp) / (1.0f + uc);
                 }
-                Codec<STORE>::st(dk + a, v, weight<DIM>(i));
+                Codec<STORE>::st(dk + a, v, weight<DIM>(i), r1);
             }
         });
     });
@@ -989,40 +1053,54 @@ __device__ __forceinline__ void outlet_fill_body(int blk, const typename Codec<S
 template <int DIM, int STORE>
 __global__ __launch_bounds__(FACE_NT) void k_outlet_fill(const typename Codec<STORE>::T *__restrict__ src,
                                                          typename Codec<STORE>::T *__restrict__ dst,
-                                                         const uint32_t *__restrict__ type, Geometry g, Boundary bd)
+                                                         const uint32_t *__restrict__ type,
+                                                         const float2 *__restrict__ psi,
+                                                         const float2 *__restrict__ ref, Geometry g, Boundary bd)
 {
-    outlet_fill_body<DIM, STORE>((int)blockIdx.x, src, dst, type, g, bd);
+    outlet_fill_body<DIM, STORE>((int)blockIdx.x, src, dst, type, psi, ref, g, bd);
 }
 
 // ---------------------------------------------------------------------------
 // State exchange: canonical f[2][Q][N] (FP64) <-> population slots.
 // ---------------------------------------------------------------------------
+// The state's own densities become the reference densities of its slots
+// (every slot of the node is read by the node itself), written to ref.
 template <int DIM, int STORE>
 __global__ void k_scatter(typename Codec<STORE>::T *__restrict__ dst, const uint32_t *__restrict__ type,
-                          Geometry g, const double *__restrict__ f)
+                          Geometry g, const double *__restrict__ f, float2 *__restrict__ ref)
 {
     constexpr int Q = Lat<DIM>::Q;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= g.N) return;
     const uint32_t tw = type[b];
-    if (tw & T_SOLID) return;
+    if (tw & T_SOLID) {
+        ref[b] = make_float2(-0.0f, -0.0f);
+        return;
+    }
     int x, y, z;
     coords_of(g, b, x, y, z);
     const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
     const int64_t bo = caller_index(g, x, y, z);
+    float rr[2];
+    for (int k = 0; k < 2; k++) {
+        double r = 0.0;
+        for (int i = 0; i < Q; i++) r += f[((int64_t)k * Q + i) * g.N + bo];
+        rr[k] = (float)r;
+    }
+    ref[b] = make_float2(rr[0], rr[1]);
     for (int k = 0; k < 2; k++) {
         auto *dk = dst + (int64_t)k * Q * g.Ppad;
         static_for<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             Codec<STORE>::st(dk + slot_of<DIM>(g, p, tw | T_EDGE, x, y, z, i),
-                             (float)f[((int64_t)k * Q + g.dmap[i]) * g.N + bo], weight<DIM>(i));
+                             (float)f[((int64_t)k * Q + g.dmap[i]) * g.N + bo], weight<DIM>(i), rr[k]);
         });
     }
 }
 
 template <int DIM, int STORE>
 __global__ void k_gather_state(const typename Codec<STORE>::T *__restrict__ src, const uint32_t *__restrict__ type,
-                               Geometry g, double *__restrict__ f)
+                               const float2 *__restrict__ ref, Geometry g, double *__restrict__ f)
 {
     constexpr int Q = Lat<DIM>::Q;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1038,7 +1116,8 @@ __global__ void k_gather_state(const typename Codec<STORE>::T *__restrict__ src,
         }
         const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
         float v[Q];
-        gather<DIM, STORE>(src + (int64_t)k * Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, v);
+        const float2 rf = ref[b];
+        gather<DIM, STORE>(src + (int64_t)k * Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, v, k == 0 ? rf.x : rf.y);
         static_for<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             f[((int64_t)k * Q + g.dmap[i]) * g.N + bo] = (double)v[i];
@@ -1072,7 +1151,8 @@ __global__ void k_feq_state(const double *__restrict__ rho0, const double *__res
 // Per-block FP64 partial sums of rho_1 and rho_2 over fluid nodes.
 template <int DIM, int STORE>
 __global__ __launch_bounds__(256) void k_mass(const typename Codec<STORE>::T *__restrict__ src,
-                                              const uint32_t *__restrict__ type, Geometry g,
+                                              const uint32_t *__restrict__ type,
+                                              const float2 *__restrict__ ref, Geometry g,
                                               double *__restrict__ part)
 {
     constexpr int Q = Lat<DIM>::Q;
@@ -1085,9 +1165,10 @@ __global__ __launch_bounds__(256) void k_mass(const typename Codec<STORE>::T *__
         coords_of(g, b, x, y, z);
         const int64_t p = pidx(g, x, y, DIM == 3 ? z : -1);
         float f[Q];
-        gather<DIM, STORE>(src, g, p, tw | T_EDGE, x, y, z, f);
+        const float2 rf = ref[b];
+        gather<DIM, STORE>(src, g, p, tw | T_EDGE, x, y, z, f, rf.x);
         static_for<Q>([&](auto ic) { m1 += (double)f[decltype(ic)::value]; });
-        gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, f);
+        gather<DIM, STORE>(src + (int64_t)Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, f, rf.y);
         static_for<Q>([&](auto ic) { m2 += (double)f[decltype(ic)::value]; });
     }
     block_sum2<256>(m1, m2, s_red);
@@ -1131,7 +1212,8 @@ __global__ __launch_bounds__(256) void k_psi_batch(BatchTab t, int cur)
     const int i = member_of(t.psi0, t.n, (int)blockIdx.x);
     const Member &m = t.m[i];
     const Geometry g = m.g;
-    psi_body<DIM, STORE>((int)blockIdx.x - t.psi0[i], (const T *)m.f[cur], m.type, g, (float2 *)m.psi);
+    psi_body<DIM, STORE>((int)blockIdx.x - t.psi0[i], (const T *)m.f[cur], m.type, g, (float2 *)m.psi[cur],
+                         (const float2 *)m.psi[cur ^ 1]);
 }
 
 // Persistent node update over the concatenated work items of all members.
@@ -1153,8 +1235,10 @@ __global__ __launch_bounds__(256) void k_main_batch(BatchTab t, int cur)
         // than hold all of them in registers
         const Member *__restrict__ m = t.m + i;
         main_item<DIM, STORE, PSRC, TX, TY, W, ZC, KEEPB>((const T *)m->f[cur], (T *)m->f[cur ^ 1], m->type,
-                                                          (const float2 *)m->psi, m->g, m->ph, m->bd, m->tiles_x,
-                                                          m->tiles_y, m->item_list[w - t.item0[i]], m->flag);
+                                                          (const float2 *)m->psi[cur],
+                                                          (const float2 *)m->psi[cur ^ 1], m->g, m->ph, m->bd,
+                                                          m->tiles_x, m->tiles_y, m->item_list[w - t.item0[i]],
+                                                          m->flag);
     }
 }
 
@@ -1171,7 +1255,8 @@ __global__ __launch_bounds__(FACE_NT) void k_outlet_batch(BatchTab t, int cur)
     using T = typename Codec<STORE>::T;
     const int i = member_of(t.out0, t.n, (int)blockIdx.x);
     const Member &m = t.m[i];
-    outlet_body<DIM, STORE>((int)blockIdx.x - t.out0[i], (const T *)m.f[cur], (T *)m.f[cur ^ 1], m.type, m.g,
+    outlet_body<DIM, STORE>((int)blockIdx.x - t.out0[i], (const T *)m.f[cur], (T *)m.f[cur ^ 1], m.type,
+                            (const float2 *)m.psi[cur], (const float2 *)m.psi[cur ^ 1], m.g,
                             m.ph, m.bd, m.flag);
 }
 
@@ -1181,7 +1266,8 @@ __global__ __launch_bounds__(FACE_NT) void k_inlet_batch(BatchTab t, int cur)
     using T = typename Codec<STORE>::T;
     const int i = member_of(t.inl0, t.n, (int)blockIdx.x);
     const Member &m = t.m[i];
-    inlet_body<DIM, STORE>((int)blockIdx.x - t.inl0[i], (T *)m.f[cur ^ 1], m.type, m.g, m.bd, m.nb_in);
+    inlet_body<DIM, STORE>((int)blockIdx.x - t.inl0[i], (T *)m.f[cur ^ 1], m.type, (const float2 *)m.psi[cur],
+                           m.g, m.bd, m.nb_in);
 }
 
 template <int DIM, int STORE>
@@ -1191,6 +1277,7 @@ __global__ __launch_bounds__(FACE_NT) void k_outlet_fill_batch(BatchTab t, int c
     const int i = member_of(t.fill0, t.n, (int)blockIdx.x);
     const Member &m = t.m[i];
     outlet_fill_body<DIM, STORE>((int)blockIdx.x - t.fill0[i], (const T *)m.f[cur], (T *)m.f[cur ^ 1], m.type,
+                                 (const float2 *)m.psi[cur], (const float2 *)m.psi[cur ^ 1],
                                  m.g, m.bd);
 }
 
@@ -1208,11 +1295,11 @@ __device__ __forceinline__ bool in_box(const Box3 &bx, int x, int y, int z)
 // rho_k of a fluid node from its post-streaming populations
 template <int DIM, int STORE>
 __device__ __forceinline__ float node_rho(const typename Codec<STORE>::T *__restrict__ src, const Geometry &g,
-                                          uint32_t tw, int x, int y, int z, int k)
+                                          uint32_t tw, int x, int y, int z, int k, float rr)
 {
     constexpr int Q = Lat<DIM>::Q;
     float f[Q];
-    gather<DIM, STORE>(src + (int64_t)k * Q * g.Ppad, g, pidx(g, x, y, DIM == 3 ? z : -1), tw, x, y, z, f);
+    gather<DIM, STORE>(src + (int64_t)k * Q * g.Ppad, g, pidx(g, x, y, DIM == 3 ? z : -1), tw, x, y, z, f, rr);
     float r = 0.0f;
     static_for<Q>([&](auto ic) { r += f[decltype(ic)::value]; });
     return r;
@@ -1221,8 +1308,9 @@ __device__ __forceinline__ float node_rho(const typename Codec<STORE>::T *__rest
 // count of dispersed nodes in the box, added to *out (zeroed by k_zero64)
 template <int DIM, int STORE>
 __global__ __launch_bounds__(256) void k_probe(const typename Codec<STORE>::T *__restrict__ src,
-                                               const uint32_t *__restrict__ type, Geometry g, int k, Box3 bx,
-                                               float thr, unsigned long long *__restrict__ out)
+                                               const uint32_t *__restrict__ type, const float2 *__restrict__ ref,
+                                               Geometry g, int k, Box3 bx, float thr,
+                                               unsigned long long *__restrict__ out)
 {
     const int ex = bx.hi[0] - bx.lo[0], ey = bx.hi[1] - bx.lo[1], ez = bx.hi[2] - bx.lo[2];
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1232,7 +1320,10 @@ __global__ __launch_bounds__(256) void k_probe(const typename Codec<STORE>::T *_
                   z = bx.lo[2] + (int)(v / ((int64_t)ex * ey));
         const int64_t b = (int64_t)x + (int64_t)g.n[0] * ((int64_t)y + (int64_t)g.n[1] * z);
         const uint32_t tw = type[b];
-        if (!(tw & T_SOLID)) hit = node_rho<DIM, STORE>(src, g, tw | T_EDGE, x, y, z, k) > thr;
+        if (!(tw & T_SOLID)) {
+            const float2 rf = ref[b];
+            hit = node_rho<DIM, STORE>(src, g, tw | T_EDGE, x, y, z, k, k == 0 ? rf.x : rf.y) > thr;
+        }
     }
     const unsigned long long c = __popcll(__ballot(hit));
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
@@ -1243,7 +1334,8 @@ static __global__ void k_zero64(unsigned long long *p) { *p = 0ull; }
 // label = own box index on dispersed nodes of the box, -1 elsewhere
 template <int DIM, int STORE>
 __global__ __launch_bounds__(256) void k_lab_init(const typename Codec<STORE>::T *__restrict__ src,
-                                                  const uint32_t *__restrict__ type, Geometry g, int k, Box3 bx,
+                                                  const uint32_t *__restrict__ type,
+                                                  const float2 *__restrict__ ref, Geometry g, int k, Box3 bx,
                                                   float thr, int *__restrict__ lab)
 {
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1252,7 +1344,10 @@ __global__ __launch_bounds__(256) void k_lab_init(const typename Codec<STORE>::T
     coords_of(g, b, x, y, z);
     const uint32_t tw = type[b];
     bool in = !(tw & T_SOLID) && in_box(bx, x, y, z);
-    if (in) in = node_rho<DIM, STORE>(src, g, tw | T_EDGE, x, y, z, k) > thr;
+    if (in) {
+        const float2 rf = ref[b];
+        in = node_rho<DIM, STORE>(src, g, tw | T_EDGE, x, y, z, k, k == 0 ? rf.x : rf.y) > thr;
+    }
     lab[b] = in ? (int)b : -1;
 }
 

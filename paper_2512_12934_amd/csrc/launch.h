@@ -44,7 +44,8 @@ struct StepArgs {
     const void *src;
     void *dst;
     const uint32_t *type;
-    float2 *psi;
+    float2 *psi;        // psi(t) (written by k_psi, or by the fused node update)
+    const float2 *ref;  // reference densities of the stored state (psi(t-1))
     Geometry g;
     Physics ph;
     Boundary bd;
@@ -72,7 +73,7 @@ template <int DIM> struct Launcher {
     static void outlet(int storage, const StepArgs &a, unsigned nb);
     static void inlet(int storage, const StepArgs &a, unsigned nb, int nb_in);
     static void outlet_fill(int storage, const StepArgs &a, unsigned nb);
-    static void scatter(int storage, const StepArgs &a, const double *f);
+    static void scatter(int storage, const StepArgs &a, const double *f, float2 *ref_out);
     static void gather_state(int storage, const StepArgs &a, double *f);
     static void feq_state(const double *rho0, const double *u0, int64_t N, double *f, hipStream_t s);
     static void mass(int storage, const StepArgs &a, double *part, int nb, double *out);

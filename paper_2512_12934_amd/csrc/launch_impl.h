@@ -20,8 +20,8 @@ void launch_cfg(const StepArgs &a)
     constexpr TileCfg c = cfg_at<DIM>(I);
     using T = typename Codec<STORE>::T;
     hipLaunchKernelGGL((k_main<DIM, STORE, c.psrc, c.tx, c.ty, c.w, c.zc, c.keepb>), dim3(a.grid), dim3(256), 0,
-                       a.stream, (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.g, a.ph, a.bd,
-                       a.tiles_x, a.tiles_y, a.items, a.item_list, a.flag);
+                       a.stream, (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.ph,
+                       a.bd, a.tiles_x, a.tiles_y, a.items, a.item_list, a.flag);
 }
 
 template <int DIM, int STORE, int... I>
@@ -62,10 +62,11 @@ void Launcher<DIM>::psi(int storage, const StepArgs &a)
 {
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
     if (storage == 0)
-        hipLaunchKernelGGL((k_psi<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.g, a.psi);
+        hipLaunchKernelGGL((k_psi<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.g, a.psi,
+                           a.ref);
     else
         hipLaunchKernelGGL((k_psi<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type, a.g,
-                           a.psi);
+                           a.psi, a.ref);
 }
 
 template <int DIM>
@@ -74,10 +75,10 @@ void Launcher<DIM>::moments(int storage, const StepArgs &a)
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
     if (storage == 0)
         hipLaunchKernelGGL((k_moments<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
-                           (const float2 *)a.psi, a.g, a.ph, a.orho, a.ou);
+                           (const float2 *)a.psi, a.ref, a.g, a.ph, a.orho, a.ou);
     else
         hipLaunchKernelGGL((k_moments<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
-                           (const float2 *)a.psi, a.g, a.ph, a.orho, a.ou);
+                           (const float2 *)a.psi, a.ref, a.g, a.ph, a.orho, a.ou);
 }
 
 template <int DIM>
@@ -99,21 +100,21 @@ void Launcher<DIM>::outlet(int storage, const StepArgs &a, unsigned nb)
 {
     if (storage == 0)
         hipLaunchKernelGGL((k_outlet<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const float *)a.src, (float *)a.dst,
-                           a.type, a.g, a.ph, a.bd, a.flag);
+                           a.type, (const float2 *)a.psi, a.ref, a.g, a.ph, a.bd, a.flag);
     else
         hipLaunchKernelGGL((k_outlet<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const __half *)a.src,
-                           (__half *)a.dst, a.type, a.g, a.ph, a.bd, a.flag);
+                           (__half *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.ph, a.bd, a.flag);
 }
 
 template <int DIM>
 void Launcher<DIM>::inlet(int storage, const StepArgs &a, unsigned nb, int nb_in)
 {
     if (storage == 0)
-        hipLaunchKernelGGL((k_inlet<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (float *)a.dst, a.type, a.g, a.bd,
-                           nb_in);
+        hipLaunchKernelGGL((k_inlet<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (float *)a.dst, a.type,
+                           (const float2 *)a.psi, a.g, a.bd, nb_in);
     else
-        hipLaunchKernelGGL((k_inlet<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (__half *)a.dst, a.type, a.g, a.bd,
-                           nb_in);
+        hipLaunchKernelGGL((k_inlet<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (__half *)a.dst, a.type,
+                           (const float2 *)a.psi, a.g, a.bd, nb_in);
 }
 
 template <int DIM>
@@ -121,21 +122,23 @@ void Launcher<DIM>::outlet_fill(int storage, const StepArgs &a, unsigned nb)
 {
     if (storage == 0)
         hipLaunchKernelGGL((k_outlet_fill<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const float *)a.src,
-                           (float *)a.dst, a.type, a.g, a.bd);
+                           (float *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.bd);
     else
         hipLaunchKernelGGL((k_outlet_fill<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const __half *)a.src,
-                           (__half *)a.dst, a.type, a.g, a.bd);
+                           (__half *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.bd);
 }
 
 template <int DIM>
-void Launcher<DIM>::scatter(int storage, const StepArgs &a, const double *f)
+void Launcher<DIM>::scatter(int storage, const StepArgs &a, const double *f, float2 *ref_out)
 {
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
-    // writes the source array (the state f(t))
+    // writes the source array (the state f(t)) and its reference densities
     if (storage == 0)
-        hipLaunchKernelGGL((k_scatter<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (float *)a.src, a.type, a.g, f);
+        hipLaunchKernelGGL((k_scatter<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (float *)a.src, a.type, a.g, f,
+                           ref_out);
     else
-        hipLaunchKernelGGL((k_scatter<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (__half *)a.src, a.type, a.g, f);
+        hipLaunchKernelGGL((k_scatter<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (__half *)a.src, a.type, a.g, f,
+                           ref_out);
 }
 
 template <int DIM>
@@ -144,10 +147,10 @@ void Launcher<DIM>::gather_state(int storage, const StepArgs &a, double *f)
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
     if (storage == 0)
         hipLaunchKernelGGL((k_gather_state<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
-                           a.g, f);
+                           a.ref, a.g, f);
     else
         hipLaunchKernelGGL((k_gather_state<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
-                           a.g, f);
+                           a.ref, a.g, f);
 }
 
 template <int DIM>
@@ -161,10 +164,10 @@ void Launcher<DIM>::mass(int storage, const StepArgs &a, double *part, int nb, d
 {
     if (storage == 0)
         hipLaunchKernelGGL((k_mass<DIM, 0>), dim3((unsigned)nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
-                           a.g, part);
+                           a.ref, a.g, part);
     else
         hipLaunchKernelGGL((k_mass<DIM, 1>), dim3((unsigned)nb), dim3(256), 0, a.stream, (const __half *)a.src,
-                           a.type, a.g, part);
+                           a.type, a.ref, a.g, part);
     hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, a.stream, (const double *)part, nb, out);
 }
 
@@ -176,11 +179,11 @@ void Launcher<DIM>::probe(int storage, const StepArgs &a, int k, const Box3 &bx,
     if (vol <= 0) return;
     const unsigned nb = (unsigned)((vol + 255) / 256);
     if (storage == 0)
-        hipLaunchKernelGGL((k_probe<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.g, k,
-                           bx, thr, out);
+        hipLaunchKernelGGL((k_probe<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.ref,
+                           a.g, k, bx, thr, out);
     else
-        hipLaunchKernelGGL((k_probe<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type, a.g,
-                           k, bx, thr, out);
+        hipLaunchKernelGGL((k_probe<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type, a.ref,
+                           a.g, k, bx, thr, out);
 }
 
 template <int DIM>
@@ -188,11 +191,11 @@ void Launcher<DIM>::lab_init(int storage, const StepArgs &a, int k, const Box3 &
 {
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
     if (storage == 0)
-        hipLaunchKernelGGL((k_lab_init<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.g,
-                           k, bx, thr, lab);
+        hipLaunchKernelGGL((k_lab_init<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
+                           a.ref, a.g, k, bx, thr, lab);
     else
         hipLaunchKernelGGL((k_lab_init<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
-                           a.g, k, bx, thr, lab);
+                           a.ref, a.g, k, bx, thr, lab);
 }
 
 template <int DIM>

@@ -42,7 +42,7 @@ struct Layout {
     bool boundary = false;
     // byte offsets into the workspace
     size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
-        o_flag, o_mpart, o_mout, o_patch, o_psi, o_items, total;
+        o_flag, o_mpart, o_mout, o_patch, o_psi[2], o_items, total;
     int cfg = 0;                   // node-update configuration (launch.h)
     int psi_mode = 1;              // 1: psi array written by k_psi, 0: recomputed in k_main
 };
@@ -449,7 +449,8 @@ Layout make_layout(const Canon &k, const Maps &m)
     L.o_mpart = take((size_t)L.nb_mass * 16);
     L.o_mout = take(16);
     L.o_patch = take(sizeof(Patch) * MAX_PATCH);
-    L.o_psi = take((size_t)g.N * 8);
+    L.o_psi[0] = take((size_t)g.N * 8);
+    L.o_psi[1] = take((size_t)g.N * 8);
     L.o_items = take(L.item_list.size() * 4);
     L.total = o;
     return L;
@@ -510,7 +511,10 @@ StepArgs step_args(const lbm_ctx *c, double *orho = nullptr, double *ou = nullpt
     a.src = c->fsrc();
     a.dst = c->fdst();
     a.type = c->type();
-    a.psi = (float2 *)(c->ws + L.o_psi);
+    // psi(t) and the reference densities of the stored state alternate
+    // with the population arrays
+    a.psi = (float2 *)(c->ws + L.o_psi[c->cur]);
+    a.ref = (const float2 *)(c->ws + L.o_psi[c->cur ^ 1]);
     a.g = L.g;
     a.ph = c->ph;
     a.bd = c->bd;
@@ -577,7 +581,13 @@ template <int DIM> struct Ops {
         c->cur ^= 1;
     }
 
-    static void scatter(lbm_ctx *c, const double *dev_f) { Lx::scatter(c->L.storage, step_args(c), dev_f); }
+    // the state and its reference densities, then psi of the state
+    static void scatter(lbm_ctx *c, const double *dev_f)
+    {
+        const StepArgs a = step_args(c);
+        Lx::scatter(c->L.storage, a, dev_f, (float2 *)(c->ws + c->L.o_psi[c->cur ^ 1]));
+        Lx::psi(c->L.storage, a);
+    }
     static void gather_state(lbm_ctx *c, double *dev_f) { Lx::gather_state(c->L.storage, step_args(c), dev_f); }
     static void mass(lbm_ctx *c, double *out)
     {
@@ -1048,7 +1058,8 @@ lbm_status lbm_batch_create(const lbm_config *cfgs, int n, void *dev_ws, size_t 
         M.f[0] = c->ws + L.o_fA;
         M.f[1] = c->ws + L.o_fB;
         M.type = c->type();
-        M.psi = c->ws + L.o_psi;
+        M.psi[0] = c->ws + L.o_psi[0];
+        M.psi[1] = c->ws + L.o_psi[1];
         M.g = L.g;
         M.ph = c->ph;
         M.bd = c->bd;

@@ -98,7 +98,8 @@ constexpr int CHI_NT = 1024;
 struct Member {
     void *f[2];                // population arrays A and B
     const uint32_t *type;
-    void *psi;                 // float2 per box node
+    void *psi[2];              // float2 per box node: psi(t) in psi[cur], the reference
+                               // densities of the stored state (psi(t-1)) in psi[cur ^ 1]
     Geometry g;
     Physics ph;
     Boundary bd;
