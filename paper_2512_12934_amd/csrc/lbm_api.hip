@@ -65,8 +65,6 @@ int lat_Q(int dim) { return dim == 2 ? 9 : 19; }
 int line_elems(int storage) { return storage == LBM_STORE_F32 ? 32 : 64; }
 int row_xoff(int storage)
 {
-    const char *e = getenv("LBM_XOFF_MODE");
-    if (e && atoi(e) == 0) return 32;
     return line_elems(storage);
 }
 int row_pitch(int n0, int storage)
