@@ -175,6 +175,13 @@ lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *ms);
  * dim.  Every configuration computes the same arithmetic per node. */
 int lbm_tile_configs(int dim);
 
+/* Describes configuration i of dim in out[6] (caller-owned): the density
+ * source (0: recomputed inside the node update, 1: a density pass before it),
+ * the lateral tile (x, then y; y is 1 in 2-D), the sweep planes per
+ * iteration, the sweep planes per work item and whether both components stay
+ * in registers.  Returns LBM_EINVAL for an unknown dim or index. */
+lbm_status lbm_tile_config_desc(int dim, int i, int *out);
+
 /* Number of steps taken; the stream is not synchronised. */
 int64_t lbm_steps_done(const lbm_ctx *ctx);
 

@@ -908,6 +908,19 @@ lbm_status lbm_time_kernels(lbm_ctx *c, int64_t n, double *ms)
 
 int lbm_tile_configs(int dim) { return (dim == 2 || dim == 3) ? n_tile_cfg(dim) : 0; }
 
+lbm_status lbm_tile_config_desc(int dim, int i, int *out)
+{
+    if (!out || (dim != 2 && dim != 3) || i < 0 || i >= n_tile_cfg(dim)) return LBM_EINVAL;
+    const TileCfg &t = tile_cfg(dim, i);
+    out[0] = t.psrc;
+    out[1] = t.tx;
+    out[2] = t.ty;
+    out[3] = t.w;
+    out[4] = t.zc;
+    out[5] = t.keepb;
+    return LBM_OK;
+}
+
 int64_t lbm_steps_done(const lbm_ctx *c) { return c ? c->steps : -1; }
 
 void lbm_destroy(lbm_ctx *c) { delete c; }

@@ -96,6 +96,8 @@ def lib():
         L.lbm_time_kernels.restype = C.c_int
         L.lbm_tile_configs.argtypes = [C.c_int]
         L.lbm_tile_configs.restype = C.c_int
+        L.lbm_tile_config_desc.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int)]
+        L.lbm_tile_config_desc.restype = C.c_int
         L.lbm_set_graph_steps.argtypes = [vp, C.c_int]
         L.lbm_steps_done.argtypes = [vp]
         L.lbm_steps_done.restype = C.c_int64
@@ -178,6 +180,16 @@ def make_config(case, storage="f32", tile_config=-1, layout="caller"):
 def tile_configs(dim):
     """Number of node-update configurations of the tuning space."""
     return int(lib().lbm_tile_configs(int(dim)))
+
+
+def tile_config_desc(dim, i):
+    """Configuration i as a dict: psi source, lateral tile, sweep planes per
+    iteration and per work item, register policy."""
+    out = (C.c_int * 6)()
+    st = lib().lbm_tile_config_desc(int(dim), int(i), out)
+    if st != LBM_OK:
+        raise LBMError(st, f"no tile configuration {i} for dim {dim}")
+    return dict(zip(("psrc", "tx", "ty", "w", "zc", "keepb"), list(out)))
 
 
 def resolve_tile_config(case, storage, tile_config):

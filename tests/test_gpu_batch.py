@@ -21,13 +21,21 @@ def _coflow_batch():
     return [cases.coflow3d(length=L, width=w, inner=i) for (L, w, i) in [(30, 8, 2), (40, 10, 4), (24, 6, 2)]]
 
 
+def _fused_config(dim):
+    """The first configuration whose node update recomputes psi itself."""
+    from paper_2512_12934_amd.lbm import tile_config_desc, tile_configs
+    return next(i for i in range(tile_configs(dim)) if tile_config_desc(dim, i)["psrc"] == 0)
+
+
 @pytest.mark.parametrize("make", [_tj_batch, _coflow_batch], ids=["tjunction", "coflow"])
 @pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_batch_equals_single_contexts_bitwise(make, storage):
+@pytest.mark.parametrize("tile", ["default", "fused"])
+def test_batch_equals_single_contexts_bitwise(make, storage, tile):
     from paper_2512_12934_amd.lbm import LBM, Batch
     cs = make()
-    print(f"[gpu] batch of {len(cs)} {cs[0].name} storage={storage}", flush=True)
-    b = Batch(cs, storage=storage)
+    cfg = -1 if tile == "default" else _fused_config(cs[0].dim)
+    print(f"[gpu] batch of {len(cs)} {cs[0].name} storage={storage} tile_config={cfg}", flush=True)
+    b = Batch(cs, storage=storage, tile_config=cfg)
     b.set_graph_steps(8)
     singles = [LBM(c, storage=storage, tile_config=b.tile_config) for c in cs]
     b.step(21)                         # two replayed graphs and an eager tail

@@ -177,22 +177,25 @@ def test_unstable_flag():
     assert e.value.status == LBM_ESTATE
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("name,make", [
     ("tjunction_small", lambda: cases.tjunction(W=20, length=90, x_side=30, side_width=14, side_len=18)),
     ("coflow_small", lambda: cases.coflow3d(length=40, width=10, inner=4)),
     ("random3d_walls", lambda: cases.random_box((34, 11, 10), seed=4, dim=3, periodic=(False, True, False),
                                                 walls=True, Gw=(0.05, -0.05), u_amp=0.01)),
+    ("random3d_periodic", lambda: cases.random_box((70, 13, 37), seed=6, dim=3, u_amp=0.01)),
+    ("random2d_periodic", lambda: cases.random_box((150, 37), seed=7, u_amp=0.01)),
 ])
-def test_tile_configs_identical(name, make):
+def test_tile_configs_identical(name, make, storage):
     """Every node-update configuration of the tuning space (tile shape, sweep
     depth, psi source, register policy) gives bitwise the same state and
-    moments as configuration 0."""
+    moments as configuration 0, with walls, periodic wraps and open faces."""
     from paper_2512_12934_amd.lbm import LBM, tile_configs
     c = make()
     ref = None
     for cfg in range(tile_configs(c.dim)):
-        print(f"[gpu] {name} tile_config={cfg}", flush=True)
-        g = LBM(c, tile_config=cfg)
+        print(f"[gpu] {name} {storage} tile_config={cfg}", flush=True)
+        g = LBM(c, storage=storage, tile_config=cfg)
         g.step(25)
         st = (g.get_state(), *g.moments(), g.mass_flux()["chi"])
         if ref is None:
