@@ -75,8 +75,8 @@ def tune(case, storage: str, steps: int, warmup: int, log=print) -> dict:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["coflow3d", "tjunction", "coflow3d_quarter", "tjunction_small"],
-                    default="coflow3d")
+    ap.add_argument("--workload", choices=["coflow3d", "tjunction", "coflow3d_quarter", "tjunction_small",
+                                           "tjunction_large"], default="coflow3d")
     ap.add_argument("--storage", choices=["f32", "f16", "both"], default="both")
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
@@ -85,7 +85,9 @@ def main(argv=None):
     sys.path.insert(0, os.path.dirname(HERE))
     from . import cases
     make = {"coflow3d": cases.coflow3d, "tjunction": cases.tjunction, "coflow3d_quarter": cases.coflow3d_quarter,
-            "tjunction_small": lambda: cases.tjunction(W=32, length=256, x_side=48, side_width=32, side_len=32)}
+            "tjunction_small": lambda: cases.tjunction(W=32, length=256, x_side=48, side_width=32, side_len=32),
+            # the sweep geometry at W = 512 (2.4M fluid nodes): the size class of large batches
+            "tjunction_large": lambda: cases.sweep_case(512, 0.01, 0.5, 1.0)}
     case = make[args.workload]()
     table = load_table()
     for storage in (["f32", "f16"] if args.storage == "both" else [args.storage]):

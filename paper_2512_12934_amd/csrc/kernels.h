@@ -318,9 +318,10 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
     constexpr int HX = TX + 4, HY = DIM == 3 ? TY + 4 : 1;
     constexpr int PLANE = HX * HY;                 // lateral halo positions per plane
     constexpr int R = W + 4;                       // ring planes
-    constexpr int NPT = DIM == 3 ? W : 1;          // nodes per thread per iteration
+    constexpr int RP = DIM == 3 ? 1 : 256 / TX;    // 2-D: rows covered by one pass of the block
+    constexpr int NPT = DIM == 3 ? W : W / RP;     // nodes per thread per iteration
     constexpr int NOFF = DIM == 3 ? 125 : 25;      // offsets of the 5^DIM stencil box
-    static_assert(DIM == 3 ? TX * LY == 256 : TX * W == 256, "256 threads per block");
+    static_assert(DIM == 3 ? TX * LY == 256 : (256 % TX == 0 && W % RP == 0), "256 threads per block");
     __shared__ float2 s_psi[R * PLANE];
     __shared__ uint8_t s_sol[R * PLANE];
 
@@ -398,7 +399,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
             for (int k = 0; k < NPT; k++) {
                 int lx, ly, sv;
                 if (DIM == 3) { lx = threadIdx.x % TX; ly = threadIdx.x / TX; sv = w0 + k; }
-                else { lx = threadIdx.x % TX; ly = 0; sv = w0 + threadIdx.x / TX; }
+                else { lx = threadIdx.x % TX; ly = 0; sv = w0 + k * RP + threadIdx.x / TX; }
                 const int x = x0 + lx;
                 const int y = DIM == 3 ? y0 + ly : sv;
                 const int z = DIM == 3 ? sv : 0;
@@ -746,7 +747,11 @@ __device__ __forceinline__ void chi_body(const Boundary &bd)
 {
     __shared__ double s_red[2 * CHI_NT / 64];
     double qin = 0.0, qout = 0.0;
+    // unrolled so that the loads of several iterations are in flight at once
+    // (the sums still run in the same sequential order per thread)
+#pragma unroll 8
     for (int j = threadIdx.x; j < bd.n_in; j += CHI_NT) qin += bd.faceQ[j];
+#pragma unroll 8
     for (int j = threadIdx.x; j < bd.n_xp; j += CHI_NT) qout += bd.faceQ[bd.n_in + j];
     block_sum2<CHI_NT>(qin, qout, s_red);
     if (threadIdx.x == 0) {
@@ -1193,6 +1198,27 @@ static __global__ void k_reduce2(const double *__restrict__ part, int n, double 
 // parity `cur` is common to all members.
 // ---------------------------------------------------------------------------
 
+// A member's descriptor is read-only for the whole launch: the batch kernels
+// read it through the constant address space, so its fields come in by
+// scalar loads into uniform registers, as kernel arguments do (through a
+// generic pointer they were vector loads, and the node update held the
+// descriptor in some twenty vector registers).
+using CMember = const __attribute__((address_space(4))) Member;
+
+// A copy of a structure held in the constant address space, word by word so
+// that it compiles to scalar loads.
+template <class S>
+__device__ __forceinline__ S const_copy(const __attribute__((address_space(4))) S *p)
+{
+    static_assert(sizeof(S) % 4 == 0, "whole words");
+    S v;
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)p;
+    uint32_t *d = (uint32_t *)&v;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(S) / 4); k++) d[k] = q[k];
+    return v;
+}
+
 // Largest i in [0, n) with start[i] <= v (start is nondecreasing, start[0] = 0).
 __device__ __forceinline__ int member_of(const int *__restrict__ start, int n, int v)
 {
@@ -1210,10 +1236,9 @@ __global__ __launch_bounds__(256) void k_psi_batch(BatchTab t, int cur)
 {
     using T = typename Codec<STORE>::T;
     const int i = member_of(t.psi0, t.n, (int)blockIdx.x);
-    const Member &m = t.m[i];
-    const Geometry g = m.g;
-    psi_body<DIM, STORE>((int)blockIdx.x - t.psi0[i], (const T *)m.f[cur], m.type, g, (float2 *)m.psi[cur],
-                         (const float2 *)m.psi[cur ^ 1]);
+    CMember *m = (CMember *)(t.m + i);
+    psi_body<DIM, STORE>((int)blockIdx.x - t.psi0[i], (const T *)m->f[cur], m->type, const_copy(&m->g),
+                         (float2 *)m->psi[cur], (const float2 *)m->psi[cur ^ 1]);
 }
 
 // Persistent node update over the concatenated work items of all members.
@@ -1230,13 +1255,13 @@ __global__ __launch_bounds__(256) void k_main_batch(BatchTab t, int cur)
     const int lo = xcd * per, hi = min(lo + per, total);
     for (int w = lo + (int)(blockIdx.x / 8); w < hi; w += slots) {
         const int i = member_of(t.item0, t.n, w);
-        // the member's descriptor is read-only for the whole launch: read it
-        // through a restrict pointer so the compiler may reload fields rather
-        // than hold all of them in registers
-        const Member *__restrict__ m = t.m + i;
+        CMember *m = (CMember *)(t.m + i);
+        const Geometry g = const_copy(&m->g);
+        const Physics ph = const_copy(&m->ph);
+        const Boundary bd = const_copy(&m->bd);
         main_item<DIM, STORE, PSRC, TX, TY, W, ZC, KEEPB>((const T *)m->f[cur], (T *)m->f[cur ^ 1], m->type,
                                                           (const float2 *)m->psi[cur],
-                                                          (const float2 *)m->psi[cur ^ 1], m->g, m->ph, m->bd,
+                                                          (const float2 *)m->psi[cur ^ 1], g, ph, bd,
                                                           m->tiles_x, m->tiles_y, m->item_list[w - t.item0[i]],
                                                           m->flag);
     }
@@ -1245,7 +1270,7 @@ __global__ __launch_bounds__(256) void k_main_batch(BatchTab t, int cur)
 // eq. (23) sums, one block per member
 static __global__ __launch_bounds__(CHI_NT) void k_chi_batch(BatchTab t)
 {
-    const Boundary bd = t.m[blockIdx.x].bd;
+    const Boundary bd = const_copy(&((CMember *)(t.m + blockIdx.x))->bd);
     if (bd.n_in + bd.n_out > 0) chi_body(bd);
 }
 
@@ -1254,10 +1279,10 @@ __global__ __launch_bounds__(FACE_NT) void k_outlet_batch(BatchTab t, int cur)
 {
     using T = typename Codec<STORE>::T;
     const int i = member_of(t.out0, t.n, (int)blockIdx.x);
-    const Member &m = t.m[i];
-    outlet_body<DIM, STORE>((int)blockIdx.x - t.out0[i], (const T *)m.f[cur], (T *)m.f[cur ^ 1], m.type,
-                            (const float2 *)m.psi[cur], (const float2 *)m.psi[cur ^ 1], m.g,
-                            m.ph, m.bd, m.flag);
+    CMember *m = (CMember *)(t.m + i);
+    outlet_body<DIM, STORE>((int)blockIdx.x - t.out0[i], (const T *)m->f[cur], (T *)m->f[cur ^ 1], m->type,
+                            (const float2 *)m->psi[cur], (const float2 *)m->psi[cur ^ 1], const_copy(&m->g),
+                            const_copy(&m->ph), const_copy(&m->bd), m->flag);
 }
 
 template <int DIM, int STORE>
@@ -1265,9 +1290,9 @@ __global__ __launch_bounds__(FACE_NT) void k_inlet_batch(BatchTab t, int cur)
 {
     using T = typename Codec<STORE>::T;
     const int i = member_of(t.inl0, t.n, (int)blockIdx.x);
-    const Member &m = t.m[i];
-    inlet_body<DIM, STORE>((int)blockIdx.x - t.inl0[i], (T *)m.f[cur ^ 1], m.type, (const float2 *)m.psi[cur],
-                           m.g, m.bd, m.nb_in);
+    CMember *m = (CMember *)(t.m + i);
+    inlet_body<DIM, STORE>((int)blockIdx.x - t.inl0[i], (T *)m->f[cur ^ 1], m->type, (const float2 *)m->psi[cur],
+                           const_copy(&m->g), const_copy(&m->bd), m->nb_in);
 }
 
 template <int DIM, int STORE>
@@ -1275,10 +1300,10 @@ __global__ __launch_bounds__(FACE_NT) void k_outlet_fill_batch(BatchTab t, int c
 {
     using T = typename Codec<STORE>::T;
     const int i = member_of(t.fill0, t.n, (int)blockIdx.x);
-    const Member &m = t.m[i];
-    outlet_fill_body<DIM, STORE>((int)blockIdx.x - t.fill0[i], (const T *)m.f[cur], (T *)m.f[cur ^ 1], m.type,
-                                 (const float2 *)m.psi[cur], (const float2 *)m.psi[cur ^ 1],
-                                 m.g, m.bd);
+    CMember *m = (CMember *)(t.m + i);
+    outlet_fill_body<DIM, STORE>((int)blockIdx.x - t.fill0[i], (const T *)m->f[cur], (T *)m->f[cur ^ 1], m->type,
+                                 (const float2 *)m->psi[cur], (const float2 *)m->psi[cur ^ 1],
+                                 const_copy(&m->g), const_copy(&m->bd));
 }
 
 // ---------------------------------------------------------------------------

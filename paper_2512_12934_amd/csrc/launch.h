@@ -24,6 +24,9 @@ constexpr TileCfg CFG2[] = {
     {1, 128, 1, 2, 16, 1},
     {1, 256, 1, 1, 16, 1},
     {0, 64, 1, 4, 16, 1},
+    {1, 64, 1, 8, 16, 1},
+    {1, 64, 1, 16, 32, 1},
+    {1, 32, 1, 16, 32, 1},
 };
 constexpr TileCfg CFG3[] = {
     {1, 32, 8, 4, 16, 1},

@@ -336,13 +336,19 @@ class _Member(LBM):
 class Batch:
     """Many contexts stepped together (one launch per stage for all members)."""
 
-    def __init__(self, case_list, storage="f32", device="cuda:0", stream=None, tile_config=-1):
+    def __init__(self, case_list, storage="f32", device="cuda:0", stream=None, tile_config="auto"):
         import torch
         L = lib()
         self.cases = list(case_list)
         n = len(self.cases)
         self.device = torch.device(device)
-        self.tile_config = resolve_tile_config(self.cases[0], storage, tile_config) if n else -1
+        if tile_config == "auto" and n:
+            # the tuned configuration of the lattice and storage for the
+            # batch's total size
+            from .autotune import lookup
+            self.tile_config = lookup(self.cases[0].dim, storage, sum(c.N for c in self.cases))
+        else:
+            self.tile_config = resolve_tile_config(self.cases[0], storage, tile_config) if n else -1
         cfgs = (Config * n)()
         self._keep = []
         for i, c in enumerate(self.cases):
