@@ -66,6 +66,13 @@ template <> struct Codec<1> {
 constexpr int BUF_FLAGS = 0x00020000;   // dword 3 of a raw gfx9 buffer descriptor
 
 template <int STORE> struct Buf;
+// Cache policy of the buffer accesses (the instruction's aux field): bit 1 is
+// the non-temporal hint.  FP32 node-update stores are non-temporal: nothing
+// reads them again within the launch, and keeping them out of the way of the
+// gathers' neighbour lines was measured faster (binary16 stores, and
+// non-temporal loads, were measured slower).
+constexpr int CPOL_NT = 2;
+
 template <> struct Buf<0> {
     static constexpr uint32_t SZ = 4;
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w, float)
@@ -75,7 +82,7 @@ template <> struct Buf<0> {
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w,
                                               float)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v - w), r, (int)vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v - w), r, (int)vo, so, CPOL_NT);
     }
 };
 template <> struct Buf<1> {
