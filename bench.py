@@ -135,6 +135,11 @@ def main():
     from paper_2512_12934_amd.lbm import LBM
 
     dev = torch.device("cuda:0")
+    # the rates plain streaming kernels reach here: the practical ceiling
+    # next to the published peak
+    from paper_2512_12934_amd.lbm import stream_probe
+    practical = stream_probe(device=dev)
+    print(f"[bench] stream probe {practical} GB/s", file=sys.stderr, flush=True)
     case = cases.coflow3d(length=args.length, width=args.width, inner=args.inner)
     fluid = case.fluid_nodes
     print(f"[bench] building {case.name} box {case.n} fluid {fluid}", file=sys.stderr, flush=True)
@@ -172,7 +177,8 @@ def main():
             "kernel": "k_main<3,%d>" % (0 if args.storage == "f32" else 1),
             "kernel_ms": round(kms[0], 5), "bytes_per_node": b_main, "nodes_per_launch": fluid,
             "mode": "two-pass (k_psi + k_main)" if two_pass else "fused (k_main only)",
-            "tile_config": sim.tile_config}
+            "tile_config": sim.tile_config,
+            "stream_probe_GBs": practical}
     del sim
     torch.cuda.empty_cache()
 

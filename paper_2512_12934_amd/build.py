@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_api.hip", "k2d.hip", "k3d.hip", "surrogate.hip"]
+SOURCES = ["lbm_api.hip", "k2d.hip", "k3d.hip", "surrogate.hip", "probe.hip"]
 HEADERS = ["kernels.h", "lattice.h", "params.h", "launch.h", "launch_impl.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,68 @@
+// probe.hip -- plain streaming kernels that measure the HBM rate a kernel of
+// a given access width can reach on this device: the practical ceiling next
+// to the published peak for the rooflines of the step kernels.
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm.h"
+
+namespace {
+
+// one 4-byte element per thread
+__global__ __launch_bounds__(256) void k_copy_b32(const uint32_t *__restrict__ a, uint32_t *__restrict__ b,
+                                                  size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// one 16-byte element per thread
+__global__ __launch_bounds__(256) void k_copy_b128(const uint4 *__restrict__ a, uint4 *__restrict__ b, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// reads one 16-byte element per thread; the sum is stored only in the
+// impossible case that it equals a NaN payload, which keeps the loads
+__global__ __launch_bounds__(256) void k_read_b128(const uint4 *__restrict__ a, uint32_t *__restrict__ out,
+                                                   size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        const uint4 v = a[i];
+        const uint32_t s = v.x ^ v.y ^ v.z ^ v.w;
+        if (s == 0x7fc0dead) out[0] = s;
+    }
+}
+
+}  // namespace
+
+extern "C" lbm_status lbm_stream_probe(const void *src, void *dst, size_t bytes, int kind, int reps,
+                                       void *hip_stream, double *gbs)
+{
+    if (!src || !dst || !gbs || bytes < 16 || bytes % 16 || kind < 0 || kind > 2 || reps < 1) return LBM_EINVAL;
+    const size_t n = kind == 0 ? bytes / 4 : bytes / 16;
+    if ((n + 255) / 256 > 0x7fffffffu) return LBM_EINVAL;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBM_EDEVICE;
+    auto launch = [&]() {
+        if (kind == 0) hipLaunchKernelGGL(k_copy_b32, grid, dim3(256), 0, s, (const uint32_t *)src, (uint32_t *)dst, n);
+        else if (kind == 1) hipLaunchKernelGGL(k_copy_b128, grid, dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n);
+        else hipLaunchKernelGGL(k_read_b128, grid, dim3(256), 0, s, (const uint4 *)src, (uint32_t *)dst, n);
+    };
+    launch();   // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; r++) launch();
+    (void)hipEventRecord(e1, s);
+    float ms = 0.0f;
+    const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+                    hipGetLastError() == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok || ms <= 0.0f) return LBM_EDEVICE;
+    const double moved = (kind == 2 ? 1.0 : 2.0) * (double)bytes * reps;
+    *gbs = moved / (ms * 1e-3) / 1e9;
+    return LBM_OK;
+}

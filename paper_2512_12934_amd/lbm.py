@@ -96,6 +96,8 @@ def lib():
         L.lbm_time_kernels.restype = C.c_int
         L.lbm_tile_configs.argtypes = [C.c_int]
         L.lbm_tile_configs.restype = C.c_int
+        L.lbm_stream_probe.argtypes = [vp, vp, C.c_size_t, C.c_int, C.c_int, vp, C.POINTER(C.c_double)]
+        L.lbm_stream_probe.restype = C.c_int
         L.lbm_tile_config_desc.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int)]
         L.lbm_tile_config_desc.restype = C.c_int
         L.lbm_set_graph_steps.argtypes = [vp, C.c_int]
@@ -180,6 +182,24 @@ def make_config(case, storage="f32", tile_config=-1, layout="caller"):
 def tile_configs(dim):
     """Number of node-update configurations of the tuning space."""
     return int(lib().lbm_tile_configs(int(dim)))
+
+
+def stream_probe(nbytes=1 << 30, reps=20, device="cuda:0"):
+    """Rates (GB/s) of plain streaming kernels on this device: copy at 4 and
+    16 bytes per thread, read at 16 bytes per thread."""
+    import torch
+    a = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+    b = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+    s = torch.cuda.current_stream(device)
+    out = {}
+    for kind, name in enumerate(("copy_b32", "copy_b128", "read_b128")):
+        r = C.c_double(0.0)
+        st = lib().lbm_stream_probe(a.data_ptr(), b.data_ptr(), nbytes, kind, reps, s.cuda_stream, C.byref(r))
+        if st != LBM_OK:
+            raise LBMError(st, "stream probe failed")
+        out[name] = round(r.value, 1)
+    del a, b
+    return out
 
 
 def tile_config_desc(dim, i):
