@@ -322,11 +322,17 @@ lbm_status surr_train(surr_ctx *ctx, const float *X, const float *Y, int n, int 
 lbm_status surr_forward_backward(surr_ctx *ctx, const float *X, const float *Y, int n, float *grads,
                                  float *loss);
 
-/* Ensemble prediction of n queries: mean and standard deviation over the
- * members of each output, and fallback[i] = 1 where some output has
- * std > threshold * |mean|. */
+/* Ensemble prediction of n queries (X, mean, std, fallback on the device).
+ * Each member's outputs are first mapped to the caller's units,
+ * y * out_scale[o] + out_shift[o] (host float[2] each; NULL = 1 and 0), so a
+ * network trained on normalised targets reports physical values.  In those
+ * units: mean [n][2] and (population) standard deviation [n][2] over the
+ * members, and fallback[i] = 1 where some output has std > threshold * |mean|
+ * (the query goes back to the lattice Boltzmann solver).  Asynchronous on the
+ * context stream.  LBM_EINVAL for bad sizes, a negative threshold or a
+ * non-finite scale or shift. */
 lbm_status surr_predict(surr_ctx *ctx, const float *X, int n, float *mean, float *std, uint8_t *fallback,
-                        float threshold);
+                        float threshold, const float *out_scale, const float *out_shift);
 
 /* Copy every member's parameters (host float [members][P], bytes exact) out
  * or in; both synchronise. */

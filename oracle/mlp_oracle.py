@@ -96,10 +96,20 @@ def forward_bf16(theta, X, H: int):
     return h2 @ p["W3"].T + p["b3"]
 
 
-def ensemble(thetas, X, H: int, threshold: float, bf16_inference=True):
-    """Mean, (population) standard deviation over members, fallback flags."""
+def ensemble(thetas, X, H: int, threshold: float, bf16_inference=True, out_scale=None, out_shift=None):
+    """Mean, (population) standard deviation over members, fallback flags.
+
+    Each member's outputs are first mapped to the caller's units,
+    y * out_scale + out_shift per output (identity by default: a network
+    trained on normalised targets gives physical values this way), and the
+    statistics and the fallback test (std > threshold * |mean| for some
+    output) are taken in those units."""
     f = forward_bf16 if bf16_inference else (lambda t, x, h: forward(t, x, h)[0])
     ys = np.stack([f(t, X, H) for t in thetas])
+    if out_scale is not None:
+        ys = ys * np.asarray(out_scale, np.float64)
+    if out_shift is not None:
+        ys = ys + np.asarray(out_shift, np.float64)
     mu = ys.mean(0)
     sd = ys.std(0)
     fb = (sd > threshold * np.abs(mu)).any(axis=1)

@@ -259,7 +259,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_predict(const float *__restrict__ params, const uint16_t *__restrict__ w2,
                                                  int members, const float *__restrict__ X, int n,
                                                  float *__restrict__ mean, float *__restrict__ sd,
-                                                 uint8_t *__restrict__ fallback, float thresh)
+                                                 uint8_t *__restrict__ fallback, float thresh, float2 oscale,
+                                                 float2 oshift)
 {
     __shared__ uint16_t s_h1[TS * H];        // layer-1 activations, BF16
     __shared__ float s_h2[TS * H];           // layer-2 activations
@@ -312,6 +313,8 @@ __global__ __launch_bounds__(256) void k_predict(const float *__restrict__ param
             const int s = tid / NOUT, o = tid % NOUT;
             float y = w[O_B3 + o];
             for (int j = 0; j < H; j++) y = fmaf(w[O_W3 + o * H + j], s_h2[s * H + j], y);
+            // the caller's units (the statistics and the fallback test use them)
+            y = o == 0 ? fmaf(y, oscale.x, oshift.x) : fmaf(y, oscale.y, oshift.y);
             s_sum[tid] += y;
             s_sq[tid] += y * y;
         }
@@ -487,10 +490,15 @@ lbm_status surr_forward_backward(surr_ctx *c, const float *X, const float *Y, in
     return LBM_OK;
 }
 
-lbm_status surr_predict(surr_ctx *c, const float *X, int n, float *mean, float *sd, uint8_t *fallback, float thresh)
+lbm_status surr_predict(surr_ctx *c, const float *X, int n, float *mean, float *sd, uint8_t *fallback, float thresh,
+                        const float *out_scale, const float *out_shift)
 {
     if (!c || !X || !mean || !sd || !fallback || n < 1 || !(thresh >= 0.0f))
         return sfail(c, LBM_EINVAL, "bad arguments to surr_predict");
+    const float2 osc = out_scale ? make_float2(out_scale[0], out_scale[1]) : make_float2(1.0f, 1.0f);
+    const float2 osh = out_shift ? make_float2(out_shift[0], out_shift[1]) : make_float2(0.0f, 0.0f);
+    if (!std::isfinite(osc.x) || !std::isfinite(osc.y) || !std::isfinite(osh.x) || !std::isfinite(osh.y))
+        return sfail(c, LBM_EINVAL, "non-finite output scale or shift");
     if (!c->w2_fresh) {
         const int64_t ne = (int64_t)c->members * H * H;
         hipLaunchKernelGGL(k_w2_bf16, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, c->stream, c->params,
@@ -498,7 +506,7 @@ lbm_status surr_predict(surr_ctx *c, const float *X, int n, float *mean, float *
         c->w2_fresh = true;
     }
     hipLaunchKernelGGL(k_predict, dim3((unsigned)((n + TS - 1) / TS)), dim3(256), 0, c->stream, c->params, c->w2,
-                       c->members, X, n, mean, sd, fallback, thresh);
+                       c->members, X, n, mean, sd, fallback, thresh, osc, osh);
     SHIPCHECK(c, hipGetLastError());
     return LBM_OK;
 }

@@ -86,10 +86,13 @@ def evaluate(sur, xs, ys, X_raw, Y_true, threshold=0.05):
     Xn = xs.fwd(X_raw).astype(np.float32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mean, sd, fb = sur.predict(Xn, threshold=threshold)
+    # the network predicts normalised labels; the kernel maps every member's
+    # outputs back to D/W and T* before the ensemble statistics, so the
+    # disagreement test is relative to the physical values
+    mean, sd, fb = sur.predict(Xn, threshold=threshold, out_scale=ys.sd, out_shift=ys.mu)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    pred = ys.inv(mean.cpu().numpy())
+    pred = mean.cpu().numpy().astype(np.float64)
     fb = fb.cpu().numpy().astype(bool)
     ape = np.abs(pred - Y_true) / np.abs(Y_true)
     keep = ~fb
@@ -98,20 +101,36 @@ def evaluate(sur, xs, ys, X_raw, Y_true, threshold=0.05):
             "fallback_rate": float(fb.mean()), "seconds_per_query": dt / len(Xn), "n": int(len(Xn))}
 
 
-def run(n_train, n_test, steps, W_range, every=100, members=5, epochs=3000, lr=3e-3, threshold=0.05,
-        seed_train=12935, seed_test=12936, log=print):
-    """Label n_train + n_test batched runs, train the ensemble on the usable
-    training labels, and judge it on the held-out ones."""
+def save_labels(path, p_tr, lab_tr, p_te, lab_te, seconds, steps):
+    """Parameters and labels of both sets as .npz (NaN where undefined)."""
+    nan = float("nan")
+    lab = lambda L: np.array([[l["D_over_W"] if l["D_over_W"] is not None else nan,
+                               l["T_star"] if l["T_star"] is not None else nan, l["passages"]] for l in L])
+    np.savez(path, params_train=np.array(p_tr, np.float64), labels_train=lab(lab_tr),
+             params_test=np.array(p_te, np.float64), labels_test=lab(lab_te),
+             lbm_seconds=np.array(seconds, np.float64), steps=steps)
+
+
+def load_labels(path):
+    """The sets written by save_labels: (p_tr, lab_tr, p_te, lab_te, seconds, steps)."""
+    z = np.load(path)
+    lab = lambda a: [{"D_over_W": None if np.isnan(r[0]) else float(r[0]),
+                      "T_star": None if np.isnan(r[1]) else float(r[1]), "passages": int(r[2])} for r in a]
+    tup = lambda a: [tuple(float(v) for v in r) for r in a]
+    return (tup(z["params_train"]), lab(z["labels_train"]), tup(z["params_test"]), lab(z["labels_test"]),
+            z["lbm_seconds"].tolist(), int(z["steps"]))
+
+
+def fit_and_judge(p_tr, lab_tr, p_te, lab_te, seconds, steps, members=5, epochs=3000, lr=3e-3,
+                  threshold=0.05):
+    """Train the ensemble on the usable training labels and judge it on the
+    usable held-out ones; seconds = LBM time of the two sets."""
     from .surrogate import Surrogate
-    p_tr = cases.sweep_params(n_train, seed_train, W_range)
-    p_te = cases.sweep_params(n_test, seed_test, W_range)
-    lab_tr, t_tr = generate(p_tr, steps, every, log=log)
-    lab_te, t_te = generate(p_te, steps, every, log=log)
     keep_tr = [i for i, l in enumerate(lab_tr) if usable(l)]
     keep_te = [i for i, l in enumerate(lab_te) if usable(l)]
-    out = {"train_runs": n_train, "test_runs": n_test, "steps": steps, "W_range": list(W_range),
+    out = {"train_runs": len(p_tr), "test_runs": len(p_te), "steps": steps,
            "usable_train": len(keep_tr), "usable_test": len(keep_te),
-           "lbm_seconds_per_run": (t_tr + t_te) / (n_train + n_test)}
+           "lbm_seconds_per_run": sum(seconds) / (len(p_tr) + len(p_te))}
     if len(keep_tr) < 8 or not keep_te:
         out["note"] = "too few labelled runs"
         return out
@@ -128,6 +147,22 @@ def run(n_train, n_test, steps, W_range, every=100, members=5, epochs=3000, lr=3
     return out
 
 
+def run(n_train, n_test, steps, W_range, every=100, members=5, epochs=3000, lr=3e-3, threshold=0.05,
+        seed_train=12935, seed_test=12936, chunk=256, labels_out=None, log=print):
+    """Label n_train + n_test batched runs (chunk instances per batch), train
+    the ensemble on the usable training labels, and judge it on the held-out
+    ones; labels_out (optional) receives the parameters and labels as .npz."""
+    p_tr = cases.sweep_params(n_train, seed_train, W_range)
+    p_te = cases.sweep_params(n_test, seed_test, W_range)
+    lab_tr, t_tr = generate(p_tr, steps, every, chunk=chunk, log=log)
+    lab_te, t_te = generate(p_te, steps, every, chunk=chunk, log=log)
+    if labels_out:
+        save_labels(labels_out, p_tr, lab_tr, p_te, lab_te, [t_tr, t_te], steps)
+    out = fit_and_judge(p_tr, lab_tr, p_te, lab_te, [t_tr, t_te], steps, members, epochs, lr, threshold)
+    out["W_range"] = list(W_range)
+    return out
+
+
 def main(argv=None):
     import argparse
     import json
@@ -138,9 +173,17 @@ def main(argv=None):
     ap.add_argument("--wmin", type=int, default=16)
     ap.add_argument("--wmax", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=3000)
+    ap.add_argument("--chunk", type=int, default=256, help="instances per batch")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--labels-out", default=None, help="write parameters and labels to this .npz")
+    ap.add_argument("--labels-in", default=None, help="train and judge on labels saved by --labels-out")
+    ap.add_argument("--threshold", type=float, default=0.05, help="ensemble disagreement that falls back")
     a = ap.parse_args(argv)
-    res = run(a.train, a.test, a.steps, (a.wmin, a.wmax), epochs=a.epochs)
+    if a.labels_in:
+        res = fit_and_judge(*load_labels(a.labels_in), epochs=a.epochs, threshold=a.threshold)
+    else:
+        res = run(a.train, a.test, a.steps, (a.wmin, a.wmax), epochs=a.epochs, threshold=a.threshold,
+                  chunk=a.chunk, labels_out=a.labels_out)
     s = json.dumps(res)
     print(s, flush=True)
     if a.out:

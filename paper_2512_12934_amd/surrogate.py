@@ -20,7 +20,7 @@ def _setup(L):
     L.surr_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.surr_train.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_float, vp]
     L.surr_forward_backward.argtypes = [vp, vp, vp, C.c_int, vp, vp]
-    L.surr_predict.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.c_float]
+    L.surr_predict.argtypes = [vp, vp, C.c_int, vp, vp, vp, C.c_float, C.POINTER(C.c_float), C.POINTER(C.c_float)]
     L.surr_get_params.argtypes = [vp, vp, C.c_size_t]
     L.surr_set_params.argtypes = [vp, vp, C.c_size_t]
     L.surr_destroy.argtypes = [vp]
@@ -88,16 +88,21 @@ class Surrogate:
                                                 len(Xd), C.c_void_p(g.data_ptr()), C.c_void_p(l.data_ptr())))
         return g.cpu().numpy(), l.cpu().numpy()
 
-    def predict(self, X, threshold=0.05):
-        """(mean [n][2], std [n][2], fallback [n]) as device tensors."""
+    def predict(self, X, threshold=0.05, out_scale=None, out_shift=None):
+        """(mean [n][2], std [n][2], fallback [n]) as device tensors, in the
+        units y * out_scale + out_shift of each output (identity by default);
+        the fallback test std > threshold * |mean| is taken in those units."""
         import torch
         Xd = self._dev(X, torch, self.device, 4)
         n = len(Xd)
         mean = torch.empty((n, 2), dtype=torch.float32, device=self.device)
         sd = torch.empty((n, 2), dtype=torch.float32, device=self.device)
         fb = torch.empty(n, dtype=torch.uint8, device=self.device)
+        sc = None if out_scale is None else (C.c_float * 2)(*[float(v) for v in out_scale])
+        sh = None if out_shift is None else (C.c_float * 2)(*[float(v) for v in out_shift])
         self._check(lib().surr_predict(self._h, C.c_void_p(Xd.data_ptr()), n, C.c_void_p(mean.data_ptr()),
-                                       C.c_void_p(sd.data_ptr()), C.c_void_p(fb.data_ptr()), float(threshold)))
+                                       C.c_void_p(sd.data_ptr()), C.c_void_p(fb.data_ptr()), float(threshold),
+                                       sc, sh))
         return mean, sd, fb
 
     def get_params(self):

@@ -67,6 +67,17 @@ def test_bf16_inference_and_ensemble_match_oracle():
     # flags agree wherever the decision is not within rounding of the threshold
     margin = np.abs(so - 0.05 * np.abs(mu)).min(axis=1) > 5e-3
     assert (fb.cpu().numpy()[margin].astype(bool) == fo[margin]).all()
+    # outputs mapped to the caller's units before the statistics
+    scale, shift = np.array([0.25, -1.5]), np.array([0.8, 4.0])
+    mean, sd, fb = s.predict(Xq, threshold=0.05, out_scale=scale, out_shift=shift)
+    torch.cuda.synchronize()
+    mu, so, fo = mo.ensemble(list(th), Xq, H, 0.05, out_scale=scale, out_shift=shift)
+    em = np.abs(mean.cpu().numpy() - mu).max()
+    es = np.abs(sd.cpu().numpy() - so).max()
+    print(f"  mapped: mean err {em:.2e}, std err {es:.2e}, fallback {fo.mean():.2f}", flush=True)
+    assert em < 4e-3 and es < 4e-3
+    margin = np.abs(so - 0.05 * np.abs(mu)).min(axis=1) > 1e-2
+    assert margin.any() and (fb.cpu().numpy()[margin].astype(bool) == fo[margin]).all()
 
 
 def test_training_is_deterministic_and_fits():

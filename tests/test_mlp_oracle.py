@@ -58,3 +58,24 @@ def test_ensemble_statistics():
     other[-2:] += 10.0                    # shift the output biases of one member
     mu, sd, fb = mo.ensemble([theta, other], X, H, 0.05)
     assert np.allclose(sd, 5.0) and fb.all()
+
+
+def test_ensemble_in_caller_units():
+    """Outputs mapped to the caller's units before the statistics: the mean
+    maps affinely, the spread scales by |scale|, and the fallback test is
+    relative to the mapped mean (a network trained on normalised targets has
+    means near zero, where a relative test on its raw outputs always fails)."""
+    H = 8
+    theta, X, _ = _rand(H)
+    other = theta.copy()
+    other[-2:] += 0.02                    # two members 0.02 apart on both raw outputs
+    mu0, sd0, fb0 = mo.ensemble([theta, other], X, H, 0.05)
+    scale, shift = np.array([0.5, -2.0]), np.array([3.0, 7.0])
+    mu, sd, fb = mo.ensemble([theta, other], X, H, 0.05, out_scale=scale, out_shift=shift)
+    assert np.allclose(mu, mu0 * scale + shift) and np.allclose(sd, sd0 * np.abs(scale))
+    assert np.allclose(sd0, 0.01)
+    # raw: spread 0.01 against means of the size of the raw outputs; mapped:
+    # 0.005 and 0.02 against means near 3 and 7, far below 5%
+    assert not fb.any()
+    small = np.abs(mu0).min(axis=1) < 0.2
+    assert small.any() and fb0[small].all()
