@@ -187,7 +187,8 @@ lbm_status lbm_tile_config_desc(int dim, int i, int *out);
  * published peak in the rooflines of the step kernels.  kind 0 copies src to
  * dst with one 4-byte element per thread (the access width of the population
  * gathers), kind 1 copies with one 16-byte element per thread, kind 2 only
- * reads src, 16 bytes per thread.  bytes (a multiple of 16, at least 16) is
+ * reads src, 16 bytes per thread, kind 3 copies eight 4-byte elements per
+ * thread (each load coalesced over the block).  bytes (a multiple of 16, at least 16) is
  * the size of src and of dst, both caller-owned device buffers.  Runs one
  * warm-up and reps timed launches on hip_stream (NULL = default) with HIP
  * events, synchronises, and writes the rate in GB/s (bytes read plus bytes

@@ -15,6 +15,19 @@ __global__ __launch_bounds__(256) void k_copy_b32(const uint32_t *__restrict__ a
     if (i < n) b[i] = a[i];
 }
 
+// eight 4-byte elements per thread, each load coalesced over the block
+__global__ __launch_bounds__(256) void k_copy_b32x8(const uint32_t *__restrict__ a, uint32_t *__restrict__ b,
+                                                    size_t n)
+{
+    const size_t i0 = (size_t)blockIdx.x * 2048 + threadIdx.x;
+    uint32_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) v[k] = i0 + 256 * k < n ? a[i0 + 256 * k] : 0u;
+#pragma unroll
+    for (int k = 0; k < 8; k++)
+        if (i0 + 256 * k < n) b[i0 + 256 * k] = v[k];
+}
+
 // one 16-byte element per thread
 __global__ __launch_bounds__(256) void k_copy_b128(const uint4 *__restrict__ a, uint4 *__restrict__ b, size_t n)
 {
@@ -40,17 +53,19 @@ __global__ __launch_bounds__(256) void k_read_b128(const uint4 *__restrict__ a, 
 extern "C" lbm_status lbm_stream_probe(const void *src, void *dst, size_t bytes, int kind, int reps,
                                        void *hip_stream, double *gbs)
 {
-    if (!src || !dst || !gbs || bytes < 16 || bytes % 16 || kind < 0 || kind > 2 || reps < 1) return LBM_EINVAL;
-    const size_t n = kind == 0 ? bytes / 4 : bytes / 16;
-    if ((n + 255) / 256 > 0x7fffffffu) return LBM_EINVAL;
-    const dim3 grid((unsigned)((n + 255) / 256));
+    if (!src || !dst || !gbs || bytes < 16 || bytes % 16 || kind < 0 || kind > 3 || reps < 1) return LBM_EINVAL;
+    const size_t n = (kind == 0 || kind == 3) ? bytes / 4 : bytes / 16;
+    const size_t per_block = kind == 3 ? 2048 : 256;
+    if ((n + per_block - 1) / per_block > 0x7fffffffu) return LBM_EINVAL;
+    const dim3 grid((unsigned)((n + per_block - 1) / per_block));
     hipStream_t s = (hipStream_t)hip_stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBM_EDEVICE;
     auto launch = [&]() {
         if (kind == 0) hipLaunchKernelGGL(k_copy_b32, grid, dim3(256), 0, s, (const uint32_t *)src, (uint32_t *)dst, n);
         else if (kind == 1) hipLaunchKernelGGL(k_copy_b128, grid, dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n);
-        else hipLaunchKernelGGL(k_read_b128, grid, dim3(256), 0, s, (const uint4 *)src, (uint32_t *)dst, n);
+        else if (kind == 2) hipLaunchKernelGGL(k_read_b128, grid, dim3(256), 0, s, (const uint4 *)src, (uint32_t *)dst, n);
+        else hipLaunchKernelGGL(k_copy_b32x8, grid, dim3(256), 0, s, (const uint32_t *)src, (uint32_t *)dst, n);
     };
     launch();   // warm-up
     (void)hipEventRecord(e0, s);
