@@ -138,7 +138,11 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes,
  * (captured on a private stream the first time, launched on the context
  * stream); the remainder, and every step enqueued while the context stream is
  * itself being captured by the caller, are launched one kernel at a time.
- * Both routes run the same kernels on the same data. */
+ * Both routes run the same kernels on the same data.  Under the caller's
+ * capture n must be even (LBM_EINVAL otherwise): the two population arrays
+ * swap every step, and an even count leaves them where every replay of the
+ * caller's graph expects them; the replays advance the device state, while
+ * lbm_steps_done counts the steps enqueued at capture once. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 
 /* Steps per replayed graph (0 = never use graphs; default 16; at most 4096).
@@ -231,7 +235,9 @@ lbm_status lbm_batch_create(const lbm_config *cfgs, int n, void *dev_ws, size_t 
 
 /* Enqueues n steps of every member on the batch stream without waiting.
  * LBM_ESTATE if a member is flagged unstable or was stepped on its own since
- * the last batch step (its A/B parity differs from the batch's). */
+ * the last batch step (its A/B parity differs from the batch's).  Under a
+ * capture of the batch stream by the caller, n must be even (as for
+ * lbm_step). */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 
 /* Steps per replayed graph for lbm_batch_step (0 = plain launches; default 16). */

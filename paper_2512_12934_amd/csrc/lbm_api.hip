@@ -758,7 +758,11 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n)
     const int G = c->graph_steps;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIPCHECK(c, hipStreamIsCapturing(c->stream, &cs));
-    // inside the caller's own capture the kernels go straight into it
+    // inside the caller's own capture the kernels go straight into it; the
+    // A/B arrays swap every step, so only an even count leaves the arrays
+    // where every replay of the caller's graph expects them
+    if (cs != hipStreamCaptureStatusNone && n % 2)
+        return fail(c, LBM_EINVAL, "a captured lbm_step must enqueue an even number of steps");
     if (G > 0 && cs == hipStreamCaptureStatusNone) {
         while (n >= G) {
             hipGraphExec_t &gx = c->gx[c->cur];
@@ -1134,6 +1138,8 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n)
     const int G = b->graph_steps;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     BHIPCHECK(b, hipStreamIsCapturing(b->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone && n % 2)
+        return bfail(b, LBM_EINVAL, "a captured lbm_batch_step must enqueue an even number of steps");
     if (G > 0 && cs == hipStreamCaptureStatusNone) {
         while (n >= G) {
             hipGraphExec_t &gx = b->gx[b->cur];

@@ -202,3 +202,38 @@ def test_tile_configs_identical(name, make, storage):
             ref = st
         for a, b in zip(st, ref):
             assert np.array_equal(a, b), cfg
+
+
+def test_caller_graph_capture_bitwise():
+    """Steps captured by the caller into a torch CUDA graph on the context
+    stream, replayed three times with eager work and synchronisations in
+    between, give the bits of the same steps launched eagerly after every
+    replay; an odd number of steps under capture is refused."""
+    import torch
+    from paper_2512_12934_amd.lbm import LBM, LBMError, LBM_EINVAL
+    c = cases.coflow3d(length=40, width=10, inner=4)
+    a = _gpu(c)
+    side = torch.cuda.Stream()            # a graph is captured on a stream of its own
+    b = LBM(c, stream=side)
+    a.set_graph_steps(0)
+    b.set_graph_steps(0)
+    a.step(2)
+    b.step(2)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=b.stream):
+        b.step(4)
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        a.step(4)
+        scratch = torch.ones(1 << 20, device="cuda:0") * (r + 1)   # unrelated eager work
+        torch.cuda.synchronize()
+        assert np.array_equal(a.get_state(), b.get_state()), r
+        assert float(scratch.sum()) == float((r + 1) << 20)
+    # an odd count under capture is refused before anything is enqueued
+    with pytest.raises(LBMError) as e:
+        g2 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g2, stream=b.stream):
+            b.step(3)
+    assert e.value.status == LBM_EINVAL
