@@ -58,6 +58,16 @@ class Case:
         return c
 
 
+# Bulk densities (phase-rich, dissolved) of the two coexisting phases at
+# G12 = 0.9 for a total near 1.05: a flat interface of the oracle started from
+# this pair in a 512-wide periodic box keeps it to 3e-3 over 40k steps, and it
+# satisfies the leading-order coexistence condition
+# c_s^2 ln(a/b) = G12 (a - b) to 1%.  Open-boundary cases feed both phases at
+# these densities: with 1.0 / 0.03 the stream of the other phase is
+# undersaturated (0.03 against ~0.09 dissolved) and dissolves the dispersed
+# phase (the 3-D co-flow device then forms no droplets).
+COEX_G09 = (0.96, 0.09)
+
 # Adhesion strength that makes the dispersed phase non-wetting (contact angle
 # ~180 degrees) at G12 = 0.9: from oracle sessile-drop runs on a 100 x 50
 # channel (drop of radius 15, 6000 steps), the contact angle grows from ~85
@@ -284,7 +294,7 @@ def channel(length: int, width: int, u_in: float, nu=(0.067, 0.067), G12: float 
 def tjunction(W: int = 100, length: int = 800, x_side: int = 150, side_width: int = 100,
               side_len: int = 100, u_c: float = 0.01, u_d: float = 0.005,
               nu=(0.067, 0.067), G12: float = 0.9, Gw_mag: float = None,
-              major: float = 1.0, minor: float = 0.03, alpha_on=True, chi_on=True) -> Case:
+              major: float = COEX_G09[0], minor: float = COEX_G09[1], alpha_on=True, chi_on=True) -> Case:
     """Main channel ``length`` x ``W`` fluid nodes between solid rows y = 0 and
     y = W+1, side channel of width ``side_width`` over x in
     [x_side, x_side+side_width) rising ``side_len`` rows above the main
@@ -325,7 +335,7 @@ def tjunction(W: int = 100, length: int = 800, x_side: int = 150, side_width: in
 
 def coflow3d(length: int = 600, width: int = 120, inner: int = 30, u_c: float = 0.02,
              u_d: float = 0.005, nu_c: float = 0.067, M: float = 5.0, G12: float = 0.9,
-             Gw_mag: float = 0.0, major: float = 1.0, minor: float = 0.03,
+             Gw_mag: float = 0.0, major: float = COEX_G09[0], minor: float = COEX_G09[1],
              alpha_on=True, chi_on=True) -> Case:
     """Square channel of ``width`` x ``width`` fluid nodes (one-node solid
     shell, so the box is length x (width+2) x (width+2)).  The x = 0 face is

@@ -45,4 +45,4 @@ def test_tjunction_regions_inside_main_channel():
 
 def test_threshold_between_bulk_densities():
     c = cases.tjunction(W=20, length=90, x_side=30, side_width=14, side_len=18)
-    assert math.isclose(labels.threshold(c), 0.5 * (1.0 + 0.03))
+    assert math.isclose(labels.threshold(c), 0.5 * (cases.COEX_G09[0] + cases.COEX_G09[1]))

@@ -1,5 +1,7 @@
 """Pins of the whole FP64 oracle step: invariants, closed-form steady states,
 Laplace's law and the paper's boundary claims."""
+import math
+
 import numpy as np
 import pytest
 
@@ -355,3 +357,27 @@ def test_adhesion_contact_angle():
     dispersed drop off the wall (contact angle 180 degrees)."""
     assert 75.0 < _contact_angle(cases.sessile(0.0), 6000) < 105.0
     assert _contact_angle(cases.sessile(cases.GW_NONWETTING), 6000) == 180.0
+
+
+def test_coexistence_pair_at_g09():
+    """The phase densities the open-boundary cases feed (cases.COEX_G09) are a
+    coexisting pair at G12 = 0.9: they satisfy the leading-order condition of
+    the two-component pseudopotential mixture, c_s^2 ln(a/b) = G12 (a - b),
+    within 1.5%, and a flat interface of the oracle started from them in a
+    wide periodic box (so the interfaces hold little of the mass) keeps both
+    bulk values to 5e-3."""
+    a, b = cases.COEX_G09
+    lhs, rhs = math.log(a / b) / 3.0, 0.9 * (a - b)
+    assert abs(lhs - rhs) < 0.015 * rhs
+    n = (512, 2, 1)
+    c = cases.Case("slab", 2, n, (True, True, True), (1.0 / 6.0, 1.0 / 6.0), 0.9,
+                   solid=np.zeros(int(np.prod(n)), np.uint8), rho0=None)
+    x, _, _ = c.grid()
+    c.rho0 = cases._rho_from_mask((x >= 128) & (x < 384), a, b)
+    s = oracle.Sim(c)
+    s.step(20000)
+    r, _, _ = s.moments()
+    r0 = r[0].reshape(n[1], n[0])[0]
+    assert abs(r0[256] - a) < 5e-3 and abs(r0[0] - b) < 5e-3
+    # the undersaturated pair 1.0 / 0.03 is not at coexistence
+    assert abs(math.log(1.0 / 0.03) / 3.0 - 0.9 * 0.97) > 0.2
