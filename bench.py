@@ -115,7 +115,7 @@ def batched(args, dev, t0, t1):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this implementation runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not an executable path.", file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -121,9 +121,9 @@ def load_labels(path):
             z["lbm_seconds"].tolist(), int(z["steps"]))
 
 
-def fit_and_judge(p_tr, lab_tr, p_te, lab_te, seconds, steps, members=5, epochs=3000, lr=3e-3,
+def fit_and_evaluate(p_tr, lab_tr, p_te, lab_te, seconds, steps, members=5, epochs=3000, lr=3e-3,
                   threshold=0.05):
-    """Train the ensemble on the usable training labels and judge it on the
+    """Train the ensemble on the usable training labels and evaluate it on the
     usable held-out ones; seconds = LBM time of the two sets."""
     from .surrogate import Surrogate
     keep_tr = [i for i, l in enumerate(lab_tr) if usable(l)]
@@ -150,7 +150,7 @@ def fit_and_judge(p_tr, lab_tr, p_te, lab_te, seconds, steps, members=5, epochs=
 def run(n_train, n_test, steps, W_range, every=100, members=5, epochs=3000, lr=3e-3, threshold=0.05,
         seed_train=12935, seed_test=12936, chunk=256, labels_out=None, log=print):
     """Label n_train + n_test batched runs (chunk instances per batch), train
-    the ensemble on the usable training labels, and judge it on the held-out
+    the ensemble on the usable training labels, and evaluate it on the held-out
     ones; labels_out (optional) receives the parameters and labels as .npz."""
     p_tr = cases.sweep_params(n_train, seed_train, W_range)
     p_te = cases.sweep_params(n_test, seed_test, W_range)
@@ -158,7 +158,7 @@ def run(n_train, n_test, steps, W_range, every=100, members=5, epochs=3000, lr=3
     lab_te, t_te = generate(p_te, steps, every, chunk=chunk, log=log)
     if labels_out:
         save_labels(labels_out, p_tr, lab_tr, p_te, lab_te, [t_tr, t_te], steps)
-    out = fit_and_judge(p_tr, lab_tr, p_te, lab_te, [t_tr, t_te], steps, members, epochs, lr, threshold)
+    out = fit_and_evaluate(p_tr, lab_tr, p_te, lab_te, [t_tr, t_te], steps, members, epochs, lr, threshold)
     out["W_range"] = list(W_range)
     return out
 
@@ -166,7 +166,7 @@ def run(n_train, n_test, steps, W_range, every=100, members=5, epochs=3000, lr=3
 def main(argv=None):
     import argparse
     import json
-    ap = argparse.ArgumentParser(description="label batched T-junction runs, train and judge the surrogate")
+    ap = argparse.ArgumentParser(description="label batched T-junction runs, train and evaluate the surrogate")
     ap.add_argument("--train", type=int, default=512)
     ap.add_argument("--test", type=int, default=64)
     ap.add_argument("--steps", type=int, default=100000)
@@ -176,11 +176,11 @@ def main(argv=None):
     ap.add_argument("--chunk", type=int, default=256, help="instances per batch")
     ap.add_argument("--out", default=None)
     ap.add_argument("--labels-out", default=None, help="write parameters and labels to this .npz")
-    ap.add_argument("--labels-in", default=None, help="train and judge on labels saved by --labels-out")
+    ap.add_argument("--labels-in", default=None, help="train and evaluate on labels saved by --labels-out")
     ap.add_argument("--threshold", type=float, default=0.05, help="ensemble disagreement that falls back")
     a = ap.parse_args(argv)
     if a.labels_in:
-        res = fit_and_judge(*load_labels(a.labels_in), epochs=a.epochs, threshold=a.threshold)
+        res = fit_and_evaluate(*load_labels(a.labels_in), epochs=a.epochs, threshold=a.threshold)
     else:
         res = run(a.train, a.test, a.steps, (a.wmin, a.wmax), epochs=a.epochs, threshold=a.threshold,
                   chunk=a.chunk, labels_out=a.labels_out)
