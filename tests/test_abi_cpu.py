@@ -83,3 +83,32 @@ def test_batch_workspace_validates(lib):
     assert lib.lbm_batch_step(None, 1) == lbm.LBM_EINVAL
     assert lib.lbm_batch_size(None) == 0
     assert lib.lbm_batch_member(None, 0) is None
+
+
+def test_size_limit_depends_on_storage(lib):
+    """A context holds each component's populations in one buffer addressed
+    with 32-bit byte offsets: a D3Q19 box of 700 x 200 x 200 needs 2.28 GB per
+    component in FP32 (refused, with the reason) and half that in binary16
+    (accepted)."""
+    import numpy as np
+    from paper_2512_12934_amd import cases, lbm
+    n = (700, 200, 200)
+    N = n[0] * n[1] * n[2]
+    c = cases.Case("big", 3, n, (True, True, True), (0.1, 0.1), 0.9, solid=np.zeros(N, np.uint8),
+                   rho0=np.ones((2, N)))
+    assert lbm.workspace_bytes(c, "f32") == 0
+    assert lbm.workspace_bytes(c, "f16") > 2 * 2 * 19 * N * 2
+    cfg, keep = lbm.make_config(c, "f32")
+    h = C.c_void_p()
+    assert lib.lbm_create(C.byref(cfg), None, 0, None, C.byref(h)) == lbm.LBM_EINVAL
+    assert b"too large" in lib.lbm_last_error(None)
+
+
+def test_all_solid_box_is_valid(lib):
+    """A box with no fluid node is a valid (empty) problem: it has a
+    workspace, and its work list is empty."""
+    import numpy as np
+    from paper_2512_12934_amd import cases, lbm
+    c = cases.random_box((20, 12, 9), seed=1, dim=3)
+    c = c.copy(solid=np.ones(c.N, np.uint8))
+    assert lbm.workspace_bytes(c) > 0
