@@ -1,0 +1,78 @@
+"""Writes coflow_quarter_oracle_labels.json: droplet labels of the FP64
+oracle on the 1/4-scale co-flow device (150 x 30 x 30 fluid, D3Q19, phases
+at the coexisting densities), for the GPU comparison in
+tests/test_gpu_labels.py.
+
+The labels are those of Sec. III D as read in the labelling code (A30):
+* the generation period: mean interval between the passages of droplet
+  fronts through a cross-section of the channel core at mid-length (counts
+  of nodes whose dispersed density exceeds the midpoint of the bulk
+  densities, sampled every 100 steps; the first two passages are the
+  start-up transient);
+* the droplet diameter: the equivalent-sphere diameter of the droplets found
+  whole between 10 and 50 nodes downstream of the inlet, sampled every 1000
+  steps, averaged.
+
+Calls only the oracle and the input generator.  About 15 minutes on 16
+threads:  python tests/golden/make_coflow_quarter_labels.py [out.json]
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+from scipy import ndimage
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2512_12934_amd import cases  # noqa: E402
+
+STEPS, EVERY, SAMPLE = 45000, 100, 1000
+LO_X, HI_X = 10, 50
+
+
+def main(out):
+    c = cases.coflow3d_quarter()
+    n0, n1, n2 = c.n
+    major = max(c.rho0[0].max(), c.rho0[1].max())
+    minor = min(c.rho0[0][c.solid == 0].min(), c.rho0[1][c.solid == 0].min())
+    thr = 0.5 * (major + minor)
+    m = n1 // 4                        # the core: a quarter of the width from each wall
+    fluid = (c.solid.reshape(n2, n1, n0) == 0)
+    s = oracle.Sim(c)
+    series, diam = [], []
+    for k in range(STEPS // EVERY):
+        s.step(EVERY)
+        rho, _, _ = s.moments()
+        r0 = rho[0].reshape(n2, n1, n0)
+        series.append(int((r0[m:n1 - m, m:n1 - m, n0 // 2] > thr).sum()))
+        if ((k + 1) * EVERY) % SAMPLE == 0:
+            field = (r0 > thr) & fluid
+            field[:, :, :LO_X] = False
+            field[:, :, HI_X:] = False
+            lab, nl = ndimage.label(field, structure=ndimage.generate_binary_structure(3, 1))
+            for j in range(1, nl + 1):
+                zz, yy, xx = np.nonzero(lab == j)
+                whole = xx.min() > LO_X and xx.max() + 1 < HI_X
+                core = min(yy.min(), zz.min()) >= m - 2 and max(yy.max(), zz.max()) + 1 <= n1 - m + 2
+                if whole and core:
+                    diam.append((6.0 * len(xx) / math.pi) ** (1.0 / 3.0))
+            print(f"[golden] step {(k + 1) * EVERY}: {len(diam)} droplet samples", flush=True)
+    on = np.asarray(series) >= 1
+    ev = (np.nonzero(on[1:] & ~on[:-1])[0] + 1)[2:]
+    period = float(np.diff(ev).mean() * EVERY) if len(ev) >= 3 else None
+    res = {"case": "coflow3d_quarter", "steps": STEPS, "every": EVERY, "threshold": thr,
+           "period_steps": period, "passages": int(len(ev) + 2),
+           "diameter": float(np.mean(diam)) if diam else None, "diameter_samples": len(diam),
+           "source": "FP64 oracle (oracle/), written by tests/golden/make_coflow_quarter_labels.py"}
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                             "coflow_quarter_oracle_labels.json"))
