@@ -549,7 +549,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                 };
                 float fo[Q];
                 const Rates ra = {ph.se[0], ph.seps[0], ph.sq, ph.snu[0]};
-                collide_pairs<DIM>(qa, r1, J1, u, F1, ra, fo);
+                collide_pairs<DIM, STORE == 0>(qa, r1, J1, u, F1, ra, fo);
                 static_for<Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     float rd = 0.0f;
@@ -562,7 +562,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     to_pairs<DIM>(f, qb);
                 }
                 const Rates rb = {ph.se[1], ph.seps[1], ph.sq, ph.snu[1]};
-                collide_pairs<DIM>(qb, r2, J2, u, F2, rb, fo);
+                collide_pairs<DIM, STORE == 0>(qb, r2, J2, u, F2, rb, fo);
                 static_for<Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     float rd = 0.0f;
@@ -826,14 +826,14 @@ __device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>
     PairF<DIM> q;
     to_pairs<DIM>(fa, q);
     const Rates s1 = {ph.se[0], ph.seps[0], ph.sq, ph.snu[0]};
-    collide_pairs<DIM>(q, r1, J1, u, F1, s1, fo);
+    collide_pairs<DIM, STORE == 0>(q, r1, J1, u, F1, s1, fo);
     static_for<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         Codec<STORE>::st(dst + (int64_t)i * g.Ppad + p, fo[i], weight<DIM>(i), dest_psi(ic).x);
     });
     to_pairs<DIM>(fb, q);
     const Rates s2 = {ph.se[1], ph.seps[1], ph.sq, ph.snu[1]};
-    collide_pairs<DIM>(q, r2, J2, u, F2, s2, fo);
+    collide_pairs<DIM, STORE == 0>(q, r2, J2, u, F2, s2, fo);
     T *d2 = dst + (int64_t)Q * g.Ppad;
     static_for<Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;

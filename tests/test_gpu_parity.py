@@ -244,7 +244,9 @@ def test_degenerate_domains(dim):
     """Edge cases of the domain: a box with no fluid node steps (its work list
     is empty) and keeps zero mass; a single fluid node enclosed by solids only
     bounces back, so it keeps its populations' mass to rounding and matches
-    the oracle."""
+    the oracle.  Rounding: FP32 storage holds f - w_i, so every stored
+    population is quantised to half an ulp of numbers up to w_0 = 1/3
+    (2^-26) whatever its own size; Q of them per step bound the mass change."""
     shape = (20, 12, 9) if dim == 3 else (30, 17)
     c = cases.random_box(shape, seed=11, dim=dim)
     empty = c.copy(solid=np.ones(c.N, np.uint8))
@@ -261,8 +263,9 @@ def test_degenerate_domains(dim):
     g.step(7)
     s.step(7)
     m1 = g.mass_flux()["mass"]
+    q = 19 if dim == 3 else 9
     for k in range(2):
-        assert abs(m1[k] - m0[k]) < 1e-6 * m0[k]
+        assert abs(m1[k] - m0[k]) <= 7 * q * 2.0 ** -26
     err = _compare_state(g, s)
     print(f"  single node: state err {err:.2e}", flush=True)
     assert err < 1e-6
