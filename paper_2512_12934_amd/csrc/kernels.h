@@ -73,11 +73,19 @@ template <int STORE> struct Buf;
 // non-temporal loads, were measured slower).
 constexpr int CPOL_NT = 2;
 
+// ld = dec(raw(...)): raw issues the load, dec turns the stored bits into the
+// population, so a caller can put independent work between the two.
 template <> struct Buf<0> {
     static constexpr uint32_t SZ = 4;
-    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w, float)
+    using Raw = uint32_t;
+    static __device__ __forceinline__ Raw raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so)
     {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, so, 0)) + w;
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, so, 0);
+    }
+    static __device__ __forceinline__ float dec(Raw h, float w, float) { return __uint_as_float(h) + w; }
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w, float rr)
+    {
+        return dec(raw(r, vo, so), w, rr);
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w,
                                               float)
@@ -87,10 +95,18 @@ template <> struct Buf<0> {
 };
 template <> struct Buf<1> {
     static constexpr uint32_t SZ = 2;
+    using Raw = unsigned short;
+    static __device__ __forceinline__ Raw raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, so, 0);
+    }
+    static __device__ __forceinline__ float dec(Raw h, float w, float rr)
+    {
+        return __half2float(__ushort_as_half(h)) + w * rr;
+    }
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w, float rr)
     {
-        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, so, 0);
-        return __half2float(__ushort_as_half(h)) + w * rr;
+        return dec(raw(r, vo, so), w, rr);
     }
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w,
                                               float rr)
@@ -170,59 +186,112 @@ __device__ __forceinline__ float gather1(const typename Codec<STORE>::T *__restr
     return Codec<STORE>::ld(fk + slot_of<DIM>(g, p, tw, x, y, z, i), weight<DIM>(i), rr);
 }
 
-// Buffer gather: for a wave whose nodes all stream in from in-box neighbours
-// (no bounce-back, no periodic wrap) population i sits at plane_i + p - off_i,
-// so the lane offset p is shared by all directions and the plane term is
-// wave-uniform.
+// Where the populations that stream into node p (pull) are stored, as byte
+// offsets within one component: a[i] per lane, plus the wave-uniform offset
+// so_i that uniform_plane() gives.  The wave takes the cheapest of three
+// address forms that is valid for all its nodes:
+// * no bounce-back and no periodic wrap (wave_fast): population i sits at
+//   plane_i + p - off_i, so a[i] is the shifted lane offset and the plane is
+//   the wave-uniform offset;
+// * walls but no wrap: per lane the streamed slot or the node's own slot of
+//   the opposite direction (bounce-back), selected without branches, with
+//   the plane in a[i];
+// * otherwise the slot of every direction from its own rule.
+// Only the addresses depend on the form; the loads are then issued in one
+// straight run for both components, so no load is pending across a join of
+// the three forms (such a join would make the loads wait for earlier ones).
 template <int DIM, int STORE>
-__device__ __forceinline__ void bgather(__amdgpu_buffer_rsrc_t rs, const Geometry &g, uint32_t p, uint32_t tw,
-                                        int x, int y, int z, bool wave_fast, float (&f)[Lat<DIM>::Q], float rr)
+__device__ __forceinline__ void gather_addr(const Geometry &g, uint32_t p, uint32_t tw, int x, int y, int z,
+                                            bool wave_fast, uint32_t (&a)[Lat<DIM>::Q])
 {
     constexpr uint32_t SZ = Buf<STORE>::SZ;
+    const uint32_t vb = (p - 1u) * SZ;
+    const uint32_t sy = (uint32_t)g.P[0] * SZ, sz = (uint32_t)g.P[0] * (uint32_t)g.P[1] * SZ;
+    const uint32_t plane = (uint32_t)g.Ppad * SZ;
+    auto shifted = [&](auto ic) -> uint32_t {
+        constexpr int i = decltype(ic)::value;
+        constexpr int ex = Lat<DIM>::E[i][0], ey = Lat<DIM>::E[i][1], ez = Lat<DIM>::E[i][2];
+        uint32_t vo = vb + (uint32_t)(1 - ex) * SZ;
+        if constexpr (ey == 1) vo -= sy;
+        if constexpr (ey == -1) vo += sy;
+        if constexpr (ez == 1) vo -= sz;
+        if constexpr (ez == -1) vo += sz;
+        return vo;
+    };
     if (wave_fast) {
-        // lane offset of x - 1 with the (y, z) part of the shift applied, so
-        // the x part is a small non-negative immediate, and the plane of
-        // direction i as the wave-uniform offset (the same plane offsets as
-        // the stores use, which keeps the uniform state small)
-        const uint32_t vb = (p - 1u) * SZ;
-        const uint32_t sy = (uint32_t)g.P[0] * SZ, sz = (uint32_t)g.P[0] * (uint32_t)g.P[1] * SZ;
-        static_for<Lat<DIM>::Q>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            constexpr int ex = Lat<DIM>::E[i][0], ey = Lat<DIM>::E[i][1], ez = Lat<DIM>::E[i][2];
-            uint32_t vo = vb + (uint32_t)(1 - ex) * SZ;
-            if constexpr (ey == 1) vo -= sy;
-            if constexpr (ey == -1) vo += sy;
-            if constexpr (ez == 1) vo -= sz;
-            if constexpr (ez == -1) vo += sz;
-            f[i] = Buf<STORE>::ld(rs, vo, (int)((int64_t)i * g.Ppad * SZ), weight<DIM>(i), rr);
-        });
+        static_for<Lat<DIM>::Q>([&](auto ic) { a[decltype(ic)::value] = shifted(ic); });
     } else if (__ballot(tw & T_EDGE) == 0) {
-        // walls but no periodic wrap in this wave: per lane either the
-        // streamed slot or the node's own slot of the opposite direction
-        // (bounce-back), selected without branches; the plane goes into the
-        // lane offset so the wave-uniform offset is zero
-        const uint32_t vb = (p - 1u) * SZ;
-        const uint32_t sy = (uint32_t)g.P[0] * SZ, sz = (uint32_t)g.P[0] * (uint32_t)g.P[1] * SZ;
-        const uint32_t plane = (uint32_t)g.Ppad * SZ;
         static_for<Lat<DIM>::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            constexpr int ex = Lat<DIM>::E[i][0], ey = Lat<DIM>::E[i][1], ez = Lat<DIM>::E[i][2];
-            uint32_t vo = vb + (uint32_t)(1 - ex) * SZ;
-            if constexpr (ey == 1) vo -= sy;
-            if constexpr (ey == -1) vo += sy;
-            if constexpr (ez == 1) vo -= sz;
-            if constexpr (ez == -1) vo += sz;
             const uint32_t own = p * SZ + (uint32_t)Lat<DIM>::OPP[i] * plane;
-            const uint32_t a = ((tw >> i) & 1u) ? own : vo + (uint32_t)i * plane;
-            f[i] = Buf<STORE>::ld(rs, a, 0, weight<DIM>(i), rr);
+            a[i] = ((tw >> i) & 1u) ? own : shifted(ic) + (uint32_t)i * plane;
         });
     } else {
         static_for<Lat<DIM>::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            const uint32_t a = (uint32_t)slot_of<DIM>(g, (int64_t)p, tw, x, y, z, i);
-            f[i] = Buf<STORE>::ld(rs, a * SZ, 0, weight<DIM>(i), rr);
+            a[i] = (uint32_t)slot_of<DIM>(g, (int64_t)p, tw, x, y, z, i) * SZ;
         });
     }
+}
+
+// The wave-uniform part of the offset of direction i (the plane in the fast form).
+template <int STORE>
+__device__ __forceinline__ int uniform_plane(const Geometry &g, bool wave_fast, int i)
+{
+    return wave_fast ? (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ) : 0;
+}
+
+// The stored bits of the populations that stream into node p, one component.
+template <int DIM, int STORE>
+__device__ __forceinline__ void bgather_raw(__amdgpu_buffer_rsrc_t rs, const Geometry &g, uint32_t p, uint32_t tw,
+                                            int x, int y, int z, bool wave_fast,
+                                            typename Buf<STORE>::Raw (&f)[Lat<DIM>::Q])
+{
+    uint32_t a[Lat<DIM>::Q];
+    gather_addr<DIM, STORE>(g, p, tw, x, y, z, wave_fast, a);
+    static_for<Lat<DIM>::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        f[i] = Buf<STORE>::raw(rs, a[i], uniform_plane<STORE>(g, wave_fast, i));
+    });
+}
+
+// The same for both components (same addresses, two buffers).
+template <int DIM, int STORE>
+__device__ __forceinline__ void bgather2_raw(__amdgpu_buffer_rsrc_t rs0, __amdgpu_buffer_rsrc_t rs1,
+                                             const Geometry &g, uint32_t p, uint32_t tw, int x, int y, int z,
+                                             bool wave_fast, typename Buf<STORE>::Raw (&f1)[Lat<DIM>::Q],
+                                             typename Buf<STORE>::Raw (&f2)[Lat<DIM>::Q])
+{
+    uint32_t a[Lat<DIM>::Q];
+    gather_addr<DIM, STORE>(g, p, tw, x, y, z, wave_fast, a);
+    static_for<Lat<DIM>::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        f1[i] = Buf<STORE>::raw(rs0, a[i], uniform_plane<STORE>(g, wave_fast, i));
+    });
+    static_for<Lat<DIM>::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        f2[i] = Buf<STORE>::raw(rs1, a[i], uniform_plane<STORE>(g, wave_fast, i));
+    });
+}
+
+// Populations from the stored bits that bgather_raw loaded.
+template <int DIM, int STORE>
+__device__ __forceinline__ void decode(const typename Buf<STORE>::Raw (&h)[Lat<DIM>::Q], float (&f)[Lat<DIM>::Q],
+                                       float rr)
+{
+    static_for<Lat<DIM>::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        f[i] = Buf<STORE>::dec(h[i], weight<DIM>(i), rr);
+    });
+}
+
+template <int DIM, int STORE>
+__device__ __forceinline__ void bgather(__amdgpu_buffer_rsrc_t rs, const Geometry &g, uint32_t p, uint32_t tw,
+                                        int x, int y, int z, bool wave_fast, float (&f)[Lat<DIM>::Q], float rr)
+{
+    typename Buf<STORE>::Raw h[Lat<DIM>::Q];
+    bgather_raw<DIM, STORE>(rs, g, p, tw, x, y, z, wave_fast, h);
+    decode<DIM, STORE>(h, f, rr);
 }
 
 __device__ __forceinline__ void coords_of(const Geometry &g, int64_t b, int &x, int &y, int &z)
@@ -387,9 +456,11 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     float f[Q];
                     float2 rf = make_float2(0.0f, 0.0f);
                     if constexpr (Codec<STORE>::REF) rf = ref[(int64_t)gx + (int64_t)g.n[0] * ((int64_t)gy + (int64_t)g.n[1] * gz)];
-                    bgather<DIM, STORE>(rs0, g, pp, tw, gx, gy, gz, wave_fast, f, rf.x);
+                    typename Buf<STORE>::Raw h1[Q], h2[Q];
+                    bgather2_raw<DIM, STORE>(rs0, rs1, g, pp, tw, gx, gy, gz, wave_fast, h1, h2);
+                    decode<DIM, STORE>(h1, f, rf.x);
                     static_for<Q>([&](auto ic) { p1 += f[decltype(ic)::value]; });
-                    bgather<DIM, STORE>(rs1, g, pp, tw, gx, gy, gz, wave_fast, f, rf.y);
+                    decode<DIM, STORE>(h2, f, rf.y);
                     static_for<Q>([&](auto ic) { p2 += f[decltype(ic)::value]; });
                 }
                 s_psi[slot] = make_float2(p1, p2);
@@ -397,22 +468,40 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
             }
         };
 
+        // node k of this thread in the sweep window starting at plane w0
+        const int lx = threadIdx.x % TX, ly = DIM == 3 ? threadIdx.x / TX : 0;
+        auto sweep_of = [&](int w0, int k) { return DIM == 3 ? w0 + k : w0 + k * RP + (int)threadIdx.x / TX; };
+        auto type_of = [&](int sv) -> uint32_t {
+            const int x = x0 + lx, y = DIM == 3 ? y0 + ly : sv, z = DIM == 3 ? sv : 0;
+            const bool valid = x < g.n[0] && sv < s1 && (DIM == 2 || y < g.n[1]);
+            return valid ? type[(int64_t)x + (int64_t)g.n[0] * ((int64_t)y + (int64_t)g.n[1] * z)] : T_SOLID;
+        };
         load_planes(s0 - 2, s0 + 2);
         for (int w0 = s0; w0 < s1; w0 += W) {
             __syncthreads();                      // ring slots of w0-6..w0-3 are free
+            // the type words of the window's nodes are loaded together with
+            // the psi planes, whose wait covers them: loaded node by node they
+            // would each wait for the previous node's stores to complete (the
+            // memory counter also counts stores)
+            uint32_t twq[NPT];
+            static_for<NPT>([&](auto jc) { twq[decltype(jc)::value] = type_of(sweep_of(w0, decltype(jc)::value)); });
             load_planes(w0 + 2, w0 + W + 2);
             __syncthreads();
+            // settle the type loads here, once per window: an empty statement
+            // that reads them, so that the wait is not placed at the head of
+            // the node loop, where it would run on every node
+#pragma unroll
+            for (int j = 0; j < NPT; j++) asm volatile("" ::"v"(twq[j]));
 #pragma unroll 1
             for (int k = 0; k < NPT; k++) {
-                int lx, ly, sv;
-                if (DIM == 3) { lx = threadIdx.x % TX; ly = threadIdx.x / TX; sv = w0 + k; }
-                else { lx = threadIdx.x % TX; ly = 0; sv = w0 + k * RP + threadIdx.x / TX; }
+                const int sv = sweep_of(w0, k);
                 const int x = x0 + lx;
                 const int y = DIM == 3 ? y0 + ly : sv;
                 const int z = DIM == 3 ? sv : 0;
                 const bool valid = x < g.n[0] && sv < s1 && (DIM == 2 || y < g.n[1]);
                 const int64_t b = valid ? (int64_t)x + (int64_t)g.n[0] * ((int64_t)y + (int64_t)g.n[1] * z) : 0;
-                const uint32_t tw = valid ? type[b] : T_SOLID;
+                const uint32_t tw = twq[0];
+                static_for<NPT - 1>([&](auto jc) { twq[decltype(jc)::value] = twq[decltype(jc)::value + 1]; });
                 const bool fluid = !(tw & T_SOLID);
                 const bool wave_fast = __ballot(fluid && (tw & (T_BBMASK | T_EDGE))) == 0;
                 if (!fluid) continue;
@@ -427,6 +516,11 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     base[d] = ((sv + d - 2 + 4 * R) % R) * PLANE + corner;
                 });
                 constexpr int CEN = (DIM == 3 ? 2 * HX : 0) + 2;   // the node itself
+                // the populations of the node: loads issued here, before the
+                // force stencil, so the LDS work below hides their latency
+                typename Buf<STORE>::Raw h1[Q], h2[Q];
+                if constexpr (KEEPB) bgather2_raw<DIM, STORE>(rs0, rs1, g, p, tw, x, y, z, wave_fast, h1, h2);
+                else bgather_raw<DIM, STORE>(rs0, g, p, tw, x, y, z, wave_fast, h1);
                 const float2 ps = s_psi[base[2] + CEN];
                 // psi(t) of the node for the next step's reference densities
                 // and the face kernels (the two-pass mode has it from k_psi)
@@ -501,10 +595,11 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                 float J1[3], J2[3];
                 {
                     float f[Q];
-                    bgather<DIM, STORE>(rs0, g, p, tw, x, y, z, wave_fast, f, rf.x);
+                    decode<DIM, STORE>(h1, f, rf.x);
                     to_pairs<DIM>(f, qa);
                     pair_momentum<DIM>(qa, J1);
-                    bgather<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, f, rf.y);
+                    if constexpr (!KEEPB) bgather_raw<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, h2);
+                    decode<DIM, STORE>(h2, f, rf.y);
                     to_pairs<DIM>(f, qb);
                     pair_momentum<DIM>(qb, J2);
                 }
@@ -620,9 +715,12 @@ __device__ __forceinline__ void psi_body(int blk, const typename Codec<STORE>::T
     float f[Q], r1 = 0.0f, r2 = 0.0f;
     float2 rf = make_float2(0.0f, 0.0f);
     if constexpr (Codec<STORE>::REF) rf = ref[b];
-    bgather<DIM, STORE>(comp_rsrc<STORE>(src, 0, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f, rf.x);
+    typename Buf<STORE>::Raw h1[Q], h2[Q];
+    bgather2_raw<DIM, STORE>(comp_rsrc<STORE>(src, 0, Q, g.Ppad), comp_rsrc<STORE>(src, 1, Q, g.Ppad), g, p, tw, x,
+                             y, z, wave_fast, h1, h2);
+    decode<DIM, STORE>(h1, f, rf.x);
     static_for<Q>([&](auto ic) { r1 += f[decltype(ic)::value]; });
-    bgather<DIM, STORE>(comp_rsrc<STORE>(src, 1, Q, g.Ppad), g, p, tw, x, y, z, wave_fast, f, rf.y);
+    decode<DIM, STORE>(h2, f, rf.y);
     static_for<Q>([&](auto ic) { r2 += f[decltype(ic)::value]; });
     psi[b] = make_float2(r1, r2);
 }
