@@ -112,6 +112,38 @@ def batched(args, dev, t0, t1):
             "speedup": round(ms / mb, 2), "create_s": round(t_create, 2)}
 
 
+def surrogate(dev, t0, t1, batch):
+    """Ensemble inference (5 members, MLP 4 -> 128 -> 128 -> 2, layer 2 on BF16
+    MFMA) over 4096 queries, timed live, beside the cost of the LBM run that
+    a query replaces: one member's share of the batched sweep just timed, over
+    a 320,000-step labelling run.  The weights are seeded random: inference
+    cost does not depend on them.  The accuracy of a trained ensemble comes
+    from the held-out study, not from this timing."""
+    import torch
+    from paper_2512_12934_amd.surrogate import Surrogate
+    n, reps, label_steps = 4096, 50, 320000
+    stream = torch.cuda.current_stream(dev)
+    s = Surrogate(members=5, hidden=128, max_n=n, seed=7, device=dev, stream=stream)
+    g = torch.Generator(device="cpu").manual_seed(11)
+    X = torch.rand((n, 4), generator=g).to(dev)
+    s.predict(X)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(reps):
+        s.predict(X)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    s.close()
+    q = ms / 1e3 / n
+    out = {"members": 5, "queries": n, "predict_ms": round(ms, 4), "s_per_query": q}
+    if batch:
+        run_s = batch["batched_ms_per_step"] / 1e3 * label_steps / batch["members"]
+        out.update({"lbm_run_s": round(run_s, 4), "lbm_run": f"{label_steps} steps of one sweep member, batched",
+                    "cost_ratio": round(run_s / q, 1)})
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -211,6 +243,7 @@ def main():
         del s3
         torch.cuda.empty_cache()
         extra["batched_sweep"] = batched(args, dev, t0, t1)
+        extra["surrogate"] = surrogate(dev, t0, t1, extra["batched_sweep"])
 
     cpu = None
     if args.cpu_seconds > 0:
