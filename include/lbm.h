@@ -192,8 +192,16 @@ lbm_status lbm_tile_config_desc(int dim, int i, int *out);
  * dst with one 4-byte element per thread (the access width of the population
  * gathers), kind 1 copies with one 16-byte element per thread, kind 2 only
  * reads src, 16 bytes per thread, kind 3 copies eight 4-byte elements per
- * thread (each load coalesced over the block).  bytes (a multiple of 16, at least 16) is
- * the size of src and of dst, both caller-owned device buffers.  Runs one
+ * thread (each load coalesced over the block).  Kinds 4 and 5 move the
+ * populations of the 3-D node update without its arithmetic: every node of a
+ * 128 x 128 x nz box loads 19 populations of two components from its
+ * neighbours' slots in 38 planes (pull streaming, as in eq. 2) and stores 38
+ * values at its own slots, 16 nodes per thread along the slowest axis; kind 4
+ * issues a node's loads after the previous node's stores, kind 5 before them.
+ * They count 304 bytes per node of the largest box that fits in the buffers
+ * (at most 2^31 - 1 bytes, and room for at least 20 planes).  bytes (a
+ * multiple of 16, at least 16) is the size of src and of dst, both
+ * caller-owned device buffers.  Runs one
  * warm-up and reps timed launches on hip_stream (NULL = default) with HIP
  * events, synchronises, and writes the rate in GB/s (bytes read plus bytes
  * written, per second) to *gbs.  LBM_EINVAL for bad arguments, LBM_EDEVICE

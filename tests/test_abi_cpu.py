@@ -112,3 +112,21 @@ def test_all_solid_box_is_valid(lib):
     c = cases.random_box((20, 12, 9), seed=1, dim=3)
     c = c.copy(solid=np.ones(c.N, np.uint8))
     assert lbm.workspace_bytes(c) > 0
+
+
+def test_stream_probe_rejects_bad_arguments(lib):
+    """Argument checks of the measurement hook answer before any device call
+    (the pointers below are never dereferenced)."""
+    from paper_2512_12934_amd.lbm import LBM_EINVAL
+    r = C.c_double(0.0)
+    fake = C.c_void_p(4096)
+    call = lambda nbytes, kind, reps=1: lib.lbm_stream_probe(fake, fake, C.c_size_t(nbytes), kind, reps, None,
+                                                             C.byref(r))
+    assert call(1 << 20, 6) == LBM_EINVAL            # unknown kind
+    assert call(1 << 20, -1) == LBM_EINVAL
+    assert call(1 << 20, 0, reps=0) == LBM_EINVAL
+    assert call(1000, 0) == LBM_EINVAL               # not a multiple of 16
+    # the pull pattern needs room for 20 planes of 128 x 128 nodes x 38 populations
+    assert call(38 * 4 * 128 * 128 * 19, 4) == LBM_EINVAL
+    assert call(1 << 31, 5) == LBM_EINVAL            # beyond 32-bit buffer offsets
+    assert lib.lbm_stream_probe(None, fake, C.c_size_t(1 << 20), 0, 1, None, C.byref(r)) == LBM_EINVAL
