@@ -35,7 +35,7 @@ struct Layout {
     int tiles[3] = {1, 1, 1};      // lateral x tiles, lateral y tiles, sweep chunks
     int64_t nblocks_main = 0;      // work items of the node update (tiles holding fluid)
     std::vector<int> item_list;    // their tile indices
-    int64_t grid_main = 0;         // launched blocks (a multiple of 8)
+    int64_t grid_main = 0;         // launched blocks (a multiple of 8 * MAIN_XCD_GROUP)
     int64_t n_slots = 0, n_in = 0, n_out = 0;
     int nb_in = 0, nb_out = 0;
     int nb_mass = 0;
@@ -420,7 +420,8 @@ Layout make_layout(const Canon &k, const Maps &m)
             if (live[it]) L.item_list.push_back((int)it);
     }
     L.nblocks_main = (int64_t)L.item_list.size();
-    L.grid_main = std::max<int64_t>((L.nblocks_main + 7) / 8 * 8, 8);
+    L.grid_main = std::max<int64_t>((L.nblocks_main + 8 * MAIN_XCD_GROUP - 1) / (8 * MAIN_XCD_GROUP) *
+                                        (8 * MAIN_XCD_GROUP), 8 * MAIN_XCD_GROUP);
     L.n_in = (int64_t)m.in.size();
     L.n_out = (int64_t)m.out.size();
     L.n_slots = 0;

@@ -93,6 +93,8 @@ struct Boundary {
 constexpr int FACE_NT = 64;
 // Threads of the single block that forms the eq. 23 sums.
 constexpr int CHI_NT = 1024;
+// Consecutive node-update work items that one XCD takes per turn.
+constexpr int MAIN_XCD_GROUP = 4;
 
 // One member of a batch: what a single context passes to its step kernels.
 struct Member {
