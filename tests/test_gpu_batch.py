@@ -77,3 +77,18 @@ def test_batch_refuses_after_a_member_stepped_alone():
         b.step(1)
     assert lib().lbm_step(b[1]._h, 1) == 0   # parities agree again
     b.step(1)
+
+
+def test_member_stepped_alone_after_batch_steps_bitwise():
+    """A member stepped on its own after batch steps (whose density pass runs
+    at the start of each batch step) computes the densities of its state first,
+    and matches a context stepped alone all along."""
+    from paper_2512_12934_amd.lbm import LBM, Batch
+    cs = _tj_batch()[:2]
+    print("[gpu] member stepped alone after batch steps", flush=True)
+    b = Batch(cs)
+    s = LBM(cs[1], tile_config=b.tile_config)
+    b.step(5)
+    b[1].step(4)
+    s.step(9)
+    assert np.array_equal(b[1].get_state(), s.get_state())
