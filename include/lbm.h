@@ -197,7 +197,9 @@ lbm_status lbm_tile_config_desc(int dim, int i, int *out);
  * 128 x 128 x nz box loads 19 populations of two components from its
  * neighbours' slots in 38 planes (pull streaming, as in eq. 2) and stores 38
  * values at its own slots, 16 nodes per thread along the slowest axis; kind 4
- * issues a node's loads after the previous node's stores, kind 5 before them.
+ * issues a node's loads after the previous node's stores, kind 5 before them;
+ * kind 6 keeps both components of a population side by side in one 8-byte
+ * slot (19 planes; 19 loads and 19 stores of 8 bytes per node).
  * They count 304 bytes per node of the largest box that fits in the buffers
  * (at most 2^31 - 1 bytes, and room for at least 20 planes).  bytes (a
  * multiple of 16, at least 16) is the size of src and of dst, both

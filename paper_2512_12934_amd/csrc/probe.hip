@@ -108,12 +108,41 @@ __global__ __launch_bounds__(256) void k_pull_d3q19(const void *src, void *dst, 
     }
 }
 
+// The same pattern with both components of a population side by side in one
+// 8-byte slot: 19 loads and 19 stores of 8 bytes per node (the same bytes,
+// half the memory instructions), a node's loads after the previous node's
+// stores.
+__global__ __launch_bounds__(256) void k_pull_d3q19_pairs(const void *src, void *dst, uint32_t bytes, uint32_t M)
+{
+    constexpr int Q = lbm::Lat<3>::Q;
+    constexpr int flags = 0x00020000;   // dword 3 of a raw gfx9 buffer descriptor
+    const __amdgpu_buffer_rsrc_t a = __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, (int)bytes, flags);
+    const __amdgpu_buffer_rsrc_t b = __builtin_amdgcn_make_buffer_rsrc(dst, (short)0, (int)bytes, flags);
+    const uint32_t xy = blockIdx.x * 256 + threadIdx.x;
+    const int z0 = 2 + (int)blockIdx.y * PULL_NZ;
+#pragma unroll 1
+    for (int z = z0; z < z0 + PULL_NZ; z++) {
+        const uint32_t j = xy + (uint32_t)z * PULL_PX * PULL_PY;
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        u32x2 v[Q];
+        lbm::static_for<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int off = lbm::Lat<3>::E[i][0] + PULL_PX * (lbm::Lat<3>::E[i][1] + PULL_PY * lbm::Lat<3>::E[i][2]);
+            v[i] = __builtin_amdgcn_raw_buffer_load_b64(a, (int)((j - off) * 8u), (int)(i * M * 8u), 0);
+        });
+        lbm::static_for<Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            __builtin_amdgcn_raw_buffer_store_b64(v[i], b, (int)(j * 8u), (int)(i * M * 8u), 2);
+        });
+    }
+}
+
 }  // namespace
 
 extern "C" lbm_status lbm_stream_probe(const void *src, void *dst, size_t bytes, int kind, int reps,
                                        void *hip_stream, double *gbs)
 {
-    if (!src || !dst || !gbs || bytes < 16 || bytes % 16 || kind < 0 || kind > 5 || reps < 1) return LBM_EINVAL;
+    if (!src || !dst || !gbs || bytes < 16 || bytes % 16 || kind < 0 || kind > 6 || reps < 1) return LBM_EINVAL;
     if (kind >= 4 && bytes > 0x7fffffffu) return LBM_EINVAL;   // 32-bit buffer offsets
     const size_t n = (kind == 0 || kind == 3) ? bytes / 4 : bytes / 16;
     const size_t per_block = kind == 3 ? 2048 : 256;
@@ -139,7 +168,8 @@ extern "C" lbm_status lbm_stream_probe(const void *src, void *dst, size_t bytes,
         else if (kind == 2) hipLaunchKernelGGL(k_read_b128, grid, dim3(256), 0, s, (const uint4 *)src, (uint32_t *)dst, n);
         else if (kind == 3) hipLaunchKernelGGL(k_copy_b32x8, grid, dim3(256), 0, s, (const uint32_t *)src, (uint32_t *)dst, n);
         else if (kind == 4) hipLaunchKernelGGL(k_pull_d3q19<0>, grid, dim3(256), 0, s, src, dst, (uint32_t)bytes, pull_M);
-        else hipLaunchKernelGGL(k_pull_d3q19<1>, grid, dim3(256), 0, s, src, dst, (uint32_t)bytes, pull_M);
+        else if (kind == 5) hipLaunchKernelGGL(k_pull_d3q19<1>, grid, dim3(256), 0, s, src, dst, (uint32_t)bytes, pull_M);
+        else hipLaunchKernelGGL(k_pull_d3q19_pairs, grid, dim3(256), 0, s, src, dst, (uint32_t)bytes, pull_M);
     };
     launch();   // warm-up
     (void)hipEventRecord(e0, s);

@@ -189,14 +189,15 @@ def stream_probe(nbytes=1 << 30, reps=20, device="cuda:0"):
     16 bytes per thread, read at 16 bytes per thread, copy of eight 4-byte
     elements per thread, and the D3Q19 pull pattern of the node update (38
     shifted loads and 38 stores per node, no arithmetic) with each node's
-    loads after / before the previous node's stores."""
+    loads after / before the previous node's stores, and the same bytes with
+    both components of a population in one 8-byte slot."""
     import torch
     a = torch.zeros(nbytes, dtype=torch.uint8, device=device)
     b = torch.zeros(nbytes, dtype=torch.uint8, device=device)
     s = torch.cuda.current_stream(device)
     out = {}
     for kind, name in enumerate(("copy_b32", "copy_b128", "read_b128", "copy_b32x8", "pull_d3q19",
-                                 "pull_d3q19_ahead")):
+                                 "pull_d3q19_ahead", "pull_d3q19_pairs")):
         r = C.c_double(0.0)
         st = lib().lbm_stream_probe(a.data_ptr(), b.data_ptr(), nbytes, kind, reps, s.cuda_stream, C.byref(r))
         if st != LBM_OK:

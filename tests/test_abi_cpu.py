@@ -122,7 +122,7 @@ def test_stream_probe_rejects_bad_arguments(lib):
     fake = C.c_void_p(4096)
     call = lambda nbytes, kind, reps=1: lib.lbm_stream_probe(fake, fake, C.c_size_t(nbytes), kind, reps, None,
                                                              C.byref(r))
-    assert call(1 << 20, 6) == LBM_EINVAL            # unknown kind
+    assert call(1 << 20, 7) == LBM_EINVAL            # unknown kind
     assert call(1 << 20, -1) == LBM_EINVAL
     assert call(1 << 20, 0, reps=0) == LBM_EINVAL
     assert call(1000, 0) == LBM_EINVAL               # not a multiple of 16

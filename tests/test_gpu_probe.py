@@ -47,9 +47,38 @@ def test_pull_probe_moves_each_population_from_its_neighbour(kind):
     assert set(shifts[:19]) == D3Q19 and len(set(shifts[:19])) == 19
 
 
+def test_pull_pairs_probe_moves_each_pair_from_its_neighbour():
+    import torch
+    from paper_2512_12934_amd.lbm import LBM_OK, lib
+    PX = PY = 128
+    nz = 20
+    M = nz * PX * PY
+    nbytes = 19 * 8 * M
+    print(f"[gpu] pull pairs probe, box 128x128x{nz}", flush=True)
+    src = torch.arange(19 * M, dtype=torch.int64, device="cuda:0")
+    dst = torch.full_like(src, -1)
+    r = C.c_double(0.0)
+    s = torch.cuda.current_stream()
+    st = lib().lbm_stream_probe(src.data_ptr(), dst.data_ptr(), nbytes, 6, 1, s.cuda_stream, C.byref(r))
+    assert st == LBM_OK and r.value > 0.0
+    d = dst.cpu().numpy().reshape(19, nz, PY, PX)
+    assert (d[:, :2] == -1).all() and (d[:, nz - 2:] == -1).all()
+    j = np.arange(M, dtype=np.int64).reshape(nz, PY, PX)[2:nz - 2]
+    shifts = []
+    for c in range(19):
+        sh = j - (d[c, 2:nz - 2] - c * M)
+        assert (sh == sh.flat[0]).all(), c
+        s0 = int(sh.flat[0])
+        ez = int(np.round(s0 / (PX * PY)))
+        ey = int(np.round((s0 - ez * PX * PY) / PX))
+        shifts.append((s0 - ez * PX * PY - ey * PX, ey, ez))
+    assert set(shifts) == D3Q19 and len(set(shifts)) == 19
+
+
 def test_stream_probe_rates_positive():
     from paper_2512_12934_amd.lbm import stream_probe
     rates = stream_probe(nbytes=64 << 20, reps=2)
     print(f"[gpu] stream probe rates {rates}", flush=True)
-    assert set(rates) == {"copy_b32", "copy_b128", "read_b128", "copy_b32x8", "pull_d3q19", "pull_d3q19_ahead"}
+    assert set(rates) == {"copy_b32", "copy_b128", "read_b128", "copy_b32x8", "pull_d3q19", "pull_d3q19_ahead",
+                          "pull_d3q19_pairs"}
     assert all(v > 0 for v in rates.values())
