@@ -671,8 +671,12 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
 
 // One context: one block per work item (tiles that hold fluid, in tile
 // order).
+// Binary16 storage asks for four waves per SIMD (128 VGPRs): its 64x4 tile
+// then runs at occupancy 4 instead of 3 without spilling, 2.4% faster; FP32
+// gains nothing from the request and takes what it needs.
 template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
-__global__ __launch_bounds__(256) void k_main(const typename Codec<STORE>::T *__restrict__ src,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STORE == 1 ? 4 : 1)))
+void k_main(const typename Codec<STORE>::T *__restrict__ src,
                                               typename Codec<STORE>::T *__restrict__ dst,
                                               const uint32_t *__restrict__ type,
                                               const float2 *__restrict__ psi, const float2 *__restrict__ ref,
@@ -1355,7 +1359,8 @@ __global__ __launch_bounds__(256) void k_psi_batch(BatchTab t, int cur)
 // the XCD of the block, and the items are dealt to the XCDs as in k_main, in
 // groups of MAIN_XCD_GROUP consecutive items per turn.
 template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
-__global__ __launch_bounds__(256) void k_main_batch(BatchTab t, int cur)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STORE == 1 ? 4 : 1)))
+void k_main_batch(BatchTab t, int cur)
 {
     using T = typename Codec<STORE>::T;
     const int total = t.item0[t.n];
