@@ -77,3 +77,34 @@ def test_batch_full_sweep_members_bitwise():
         fm, fs = b.members[i].mass_flux(), s.mass_flux()
         for key in ("q_in", "q_out", "chi", "u_conv"):
             assert fm[key] == fs[key], (i, key)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 3e-5), ("f16", 1e-3)])
+def test_tjunction_4096x1026_full_size(storage, tol):
+    """The largest T-junction of the sweep distribution (W 512, 4096 x 1026
+    box, 2.36M fluid nodes, D2Q9) in the configuration the autotuner picks
+    for it (the fused node update): three steps against the FP64 oracle on
+    every fluid node, and the eq. 23 sums of the last step."""
+    from paper_2512_12934_amd.lbm import LBM
+    c = cases.sweep_case(512, 0.01, 0.5, 1.0)
+    steps = 3
+    print(f"[gpu] T-junction full size {c.n} storage={storage}", flush=True)
+    g = LBM(c, storage=storage, tile_config="auto")
+    g.step(steps)
+    rg, ug = g.moments()
+    fg = g.mass_flux()
+    del g
+    s = oracle.Sim(c)
+    s.step(steps)
+    ro, uo, _ = s.moments()
+    do = s.diag()
+    s.close()
+    fluid = c.solid == 0
+    rt = ro[:, fluid].sum(axis=0)
+    er = (np.abs(rg[:, fluid] - ro[:, fluid]) / rt).max()
+    eu = np.abs(ug[:, fluid] - uo[:, fluid]).max() / np.abs(uo[:, fluid]).max()
+    print(f"  rho err / node density {er:.3e}, u err / max|u| {eu:.3e}", flush=True)
+    assert np.isfinite(rg[:, fluid]).all() and np.isfinite(ug[:, fluid]).all()
+    assert er < tol and eu < 10 * tol
+    for key in ("q_in", "q_out", "chi"):
+        assert abs(fg[key] - do[key]) <= 10 * tol * abs(do[key]), key
