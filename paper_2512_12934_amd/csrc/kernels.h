@@ -400,6 +400,12 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
     static_assert(DIM == 3 ? TX * LY == 256 : (256 % TX == 0 && W % RP == 0), "256 threads per block");
     __shared__ float2 s_psi[R * PLANE];
     __shared__ uint8_t s_sol[R * PLANE];
+    // 2-D fused mode, binary16: the stored bits of the populations that
+    // stream into each ring node, gathered once for its psi and read back by
+    // the node update (the same loads, so the same bits).  FP32 would need
+    // 39 KB of LDS per block and lose more occupancy than it saves.
+    constexpr bool STAGE = DIM == 2 && PSRC == 0 && STORE == 1;
+    __shared__ typename Buf<STORE>::Raw s_fr[STAGE ? R * PLANE * 2 * Q : 1];
 
     const __amdgpu_buffer_rsrc_t rs0 = comp_rsrc<STORE>(src, 0, Q, g.Ppad);
     const __amdgpu_buffer_rsrc_t rs1 = comp_rsrc<STORE>(src, 1, Q, g.Ppad);
@@ -458,6 +464,13 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     if constexpr (Codec<STORE>::REF) rf = ref[(int64_t)gx + (int64_t)g.n[0] * ((int64_t)gy + (int64_t)g.n[1] * gz)];
                     typename Buf<STORE>::Raw h1[Q], h2[Q];
                     bgather2_raw<DIM, STORE>(rs0, rs1, g, pp, tw, gx, gy, gz, wave_fast, h1, h2);
+                    if constexpr (STAGE) {
+                        static_for<Q>([&](auto ic) {
+                            constexpr int i = decltype(ic)::value;
+                            s_fr[slot * 2 * Q + i] = h1[i];
+                            s_fr[slot * 2 * Q + Q + i] = h2[i];
+                        });
+                    }
                     decode<DIM, STORE>(h1, f, rf.x);
                     static_for<Q>([&](auto ic) { p1 += f[decltype(ic)::value]; });
                     decode<DIM, STORE>(h2, f, rf.y);
@@ -519,8 +532,19 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                 // the populations of the node: loads issued here, before the
                 // force stencil, so the LDS work below hides their latency
                 typename Buf<STORE>::Raw h1[Q], h2[Q];
-                if constexpr (KEEPB) bgather2_raw<DIM, STORE>(rs0, rs1, g, p, tw, x, y, z, wave_fast, h1, h2);
-                else bgather_raw<DIM, STORE>(rs0, g, p, tw, x, y, z, wave_fast, h1);
+                if constexpr (STAGE) {
+                    // staged in the ring when psi of this node's plane was formed
+                    const int sl = base[2] + CEN;
+                    static_for<Q>([&](auto ic) {
+                        constexpr int i = decltype(ic)::value;
+                        h1[i] = s_fr[sl * 2 * Q + i];
+                        h2[i] = s_fr[sl * 2 * Q + Q + i];
+                    });
+                } else if constexpr (KEEPB) {
+                    bgather2_raw<DIM, STORE>(rs0, rs1, g, p, tw, x, y, z, wave_fast, h1, h2);
+                } else {
+                    bgather_raw<DIM, STORE>(rs0, g, p, tw, x, y, z, wave_fast, h1);
+                }
                 const float2 ps = s_psi[base[2] + CEN];
                 // psi(t) of the node for the next step's reference densities
                 // and the face kernels (the two-pass mode has it from k_psi)
@@ -598,7 +622,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     decode<DIM, STORE>(h1, f, rf.x);
                     to_pairs<DIM>(f, qa);
                     pair_momentum<DIM>(qa, J1);
-                    if constexpr (!KEEPB) bgather_raw<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, h2);
+                    if constexpr (!KEEPB && !STAGE) bgather_raw<DIM, STORE>(rs1, g, p, tw, x, y, z, wave_fast, h2);
                     decode<DIM, STORE>(h2, f, rf.y);
                     to_pairs<DIM>(f, qb);
                     pair_momentum<DIM>(qb, J2);
