@@ -1393,7 +1393,7 @@ void k_main_batch(BatchTab t, int cur)
         const int S = v / 8, r = v % 8;
         const int w = ((S / MAIN_XCD_GROUP) * 8 + r) * MAIN_XCD_GROUP + S % MAIN_XCD_GROUP;
         if (w >= total) continue;
-        const int i = member_of(t.item0, t.n, w);
+        const int i = __builtin_amdgcn_readfirstlane(t.item_mem[w]);
         CMember *m = (CMember *)(t.m + i);
         const Geometry g = const_copy(&m->g);
         const Physics ph = const_copy(&m->ph);

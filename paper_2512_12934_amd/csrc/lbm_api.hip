@@ -987,21 +987,24 @@ std::string batch_plan(const lbm_config *cfgs, int n, std::vector<lbm_config> &m
     bytes.assign(n, 0);
     const int cfg = cfgs[0].tile_config;
     total = 0;
+    int64_t items = 0;
     for (int i = 0; i < n; i++) {
         if (mc[i].dim != mc[0].dim || mc[i].storage != mc[0].storage)
             return "batch members must share the lattice and the storage";
         mc[i].tile_config = cfg;
-        bytes[i] = lbm_workspace_bytes(&mc[i]);
-        if (!bytes[i]) {
-            Canon k;
-            std::string why = canonicalize(&mc[i], k);
-            Maps m;
-            if (why.empty()) why = build_maps(&k.c, m);
-            return "member " + std::to_string(i) + ": " + why;
-        }
+        Canon k;
+        std::string why = canonicalize(&mc[i], k);
+        Maps m;
+        if (why.empty()) why = build_maps(&k.c, m);
+        if (!why.empty()) return "member " + std::to_string(i) + ": " + why;
+        const Layout L = make_layout(k, m);
+        bytes[i] = L.total;
+        items += (int64_t)L.item_list.size();
         total += align_up(bytes[i]);
     }
-    tables = align_up(sizeof(Member) * n) + 5 * align_up(sizeof(int) * (n + 1));
+    if (items > INT32_MAX) return "too many node-update work items";
+    tables = align_up(sizeof(Member) * n) + 5 * align_up(sizeof(int) * (n + 1)) +
+             align_up(sizeof(int) * std::max<int64_t>(items, 1));
     total += tables;
     return "";
 }
@@ -1103,11 +1106,16 @@ lbm_status lbm_batch_create(const lbm_config *cfgs, int n, void *dev_ws, size_t 
     b->tab.n = n;
     b->tab.m = (const Member *)put(mem.data(), sizeof(Member) * n);
     b->tab.item0 = (const int *)put(item0.data(), sizeof(int) * (n + 1));
+    std::vector<int> item_mem(std::max(item0[n], 1), 0);
+    for (int i = 0; i < n; i++)
+        for (int w = item0[i]; w < item0[i + 1]; w++) item_mem[w] = i;
+    b->tab.item_mem = (const int *)put(item_mem.data(), sizeof(int) * item_mem.size());
     b->tab.psi0 = (const int *)put(psi0.data(), sizeof(int) * (n + 1));
     b->tab.out0 = (const int *)put(out0.data(), sizeof(int) * (n + 1));
     b->tab.inl0 = (const int *)put(inl0.data(), sizeof(int) * (n + 1));
     b->tab.fill0 = (const int *)put(fill0.data(), sizeof(int) * (n + 1));
-    if (!b->tab.m || !b->tab.item0 || !b->tab.psi0 || !b->tab.out0 || !b->tab.inl0 || !b->tab.fill0) {
+    if (!b->tab.m || !b->tab.item0 || !b->tab.item_mem || !b->tab.psi0 || !b->tab.out0 || !b->tab.inl0 ||
+        !b->tab.fill0) {
         delete b;
         return bfail(nullptr, LBM_EDEVICE, "upload of the batch tables failed");
     }

@@ -118,6 +118,7 @@ struct BatchTab {
     const Member *m;
     int n;
     const int *item0;          // node-update work items
+    const int *item_mem;       // the member of each node-update work item
     const int *psi0;           // k_psi blocks
     const int *out0;           // outlet-collision blocks
     const int *inl0;           // inlet-kernel blocks (inlet nodes, then U_c partials)
