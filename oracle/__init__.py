@@ -83,8 +83,23 @@ def lib():
         L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
         L.orc_nodes.argtypes = [C.c_void_p]
         L.orc_nodes.restype = C.c_int64
+        L.orc_set_next.argtypes = [C.c_void_p, _dp]
+        L.orc_get_next.argtypes = [C.c_void_p, _dp]
+        L.orc_set_force.argtypes = [C.c_void_p, _dp]
+        L.orc_stage.argtypes = [C.c_void_p, C.c_int]
+        L.orc_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         _LIB = L
     return _LIB
+
+
+def threads():
+    """OpenMP threads the oracle's node loops run on."""
+    return int(lib().orc_threads())
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
 
 
 def _ptr(a):
@@ -238,3 +253,18 @@ class Sim:
         d = Diag()
         lib().orc_diagnostics(self._h, C.byref(d))
         return d.as_dict()
+
+    # -- test hooks: single stages on a planted state (see lbm_oracle.h) --
+    def set_next(self, fn):
+        lib().orc_set_next(self._h, _ptr(_f64(fn)))
+
+    def get_next(self):
+        fn = np.zeros((2, self.q, self.N))
+        lib().orc_get_next(self._h, _ptr(fn))
+        return fn
+
+    def set_force(self, F):
+        lib().orc_set_force(self._h, _ptr(_f64(F)))
+
+    def stage(self, k):
+        lib().orc_stage(self._h, int(k))

@@ -30,6 +30,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define QMAX 19
 #define KMAX 92
@@ -54,6 +57,14 @@ static const int E3[19][3] = {
     {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
 
 int orc_Q(int dim) { return dim == 2 ? 9 : 19; }
+
+#ifdef _OPENMP
+int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+#else
+int orc_threads(void) { return 1; }
+void orc_set_threads(int n) { (void)n; }
+#endif
 
 static const int (*lat_e(int dim))[3] { return dim == 2 ? E2 : E3; }
 
@@ -819,3 +830,30 @@ void orc_moments(orc_sim *s, double *rho, double *u, double *F)
 }
 
 void orc_diagnostics(orc_sim *s, orc_diag *d) { *d = s->diag; }
+
+void orc_set_next(orc_sim *s, const double *fn)
+{
+    memcpy(s->fn, fn, sizeof(double) * 2 * (size_t)s->Q * s->N);
+}
+
+void orc_get_next(const orc_sim *s, double *fn)
+{
+    memcpy(fn, s->fn, sizeof(double) * 2 * (size_t)s->Q * s->N);
+}
+
+void orc_set_force(orc_sim *s, const double *F)
+{
+    memcpy(s->F, F, sizeof(double) * 6 * (size_t)s->N);
+}
+
+void orc_stage(orc_sim *s, int stage)
+{
+    switch (stage) {
+    case 1: stage_moments_forces(s); break;
+    case 4: stage_outlet_velocity(s); break;
+    case 5: stage_collide_stream(s); break;
+    case 7: stage_inlet(s); break;
+    case 8: stage_outlet_fill(s); break;
+    default: break;
+    }
+}

@@ -96,6 +96,10 @@ void orc_collide_node(int dim, const double *s, const double *f, double rho,
 /* Force stencil: returns the number of neighbours; off [K][3], w [K]. */
 int  orc_stencil(int dim, int *off, double *w);
 
+/* ---- OpenMP threads of the node loops (timing only) ---- */
+int  orc_threads(void);
+void orc_set_threads(int n);
+
 /* ---- whole-domain simulation ---- */
 orc_sim *orc_create(const orc_params *p, const uint8_t *solid,
                     const double *rho0, const double *u0);
@@ -107,6 +111,18 @@ void orc_set_f(orc_sim *s, const double *f);
  * override), F [2][3][N] (total force on each component).  Any may be NULL. */
 void orc_moments(orc_sim *s, double *rho, double *u, double *F);
 void orc_diagnostics(orc_sim *s, orc_diag *d);
+
+/* ---- test hooks: single stages of a step on a planted state ----
+ * fn is the buffer of f(t+1) that streaming fills and stages 7-8 complete
+ * ([2][Q][N]); F is the force of stage 2 ([2][3][N]).  orc_stage runs one
+ * stage of the step on the current buffers without swapping them:
+ * 1 = stages 1-3 (densities, forces, velocity from f), 4 = outlet velocity
+ * correction, 5 = collision and streaming (stages 5-6), 7 = inlet,
+ * 8 = convective outflow. */
+void orc_set_next(orc_sim *s, const double *fn);
+void orc_get_next(const orc_sim *s, double *fn);
+void orc_set_force(orc_sim *s, const double *F);
+void orc_stage(orc_sim *s, int stage);
 int64_t orc_nodes(const orc_sim *s);
 
 #ifdef __cplusplus
