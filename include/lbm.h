@@ -146,7 +146,11 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes,
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 
 /* Steps per replayed graph (0 = never use graphs; default 16; at most 4096).
- * Drops graphs captured so far.  LBM_EINVAL for a value out of range. */
+ * Drops graphs captured so far, then captures, instantiates and uploads the
+ * graphs of both A/B parities at once, so that later lbm_step calls replay
+ * them without a capture (set-up work, not to be called inside the caller's
+ * own capture).  LBM_EINVAL for a value out of range, LBM_EDEVICE if a
+ * capture fails. */
 lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int steps_per_graph);
 
 /* Synchronises the stream and writes rho [2][N] and the common velocity
@@ -250,7 +254,9 @@ lbm_status lbm_batch_create(const lbm_config *cfgs, int n, void *dev_ws, size_t 
  * lbm_step). */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 
-/* Steps per replayed graph for lbm_batch_step (0 = plain launches; default 16). */
+/* Steps per replayed graph for lbm_batch_step (0 = plain launches; default
+ * 16).  As lbm_set_graph_steps: both parities are captured and uploaded at
+ * once. */
 lbm_status lbm_batch_set_graph_steps(lbm_batch *b, int steps_per_graph);
 
 /* Number of members; 0 for NULL. */

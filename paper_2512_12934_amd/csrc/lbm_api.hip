@@ -623,6 +623,32 @@ lbm_status check_flag(lbm_ctx *c)
     return c->unstable ? LBM_EUNSTABLE : LBM_OK;
 }
 
+// Captures graph_steps steps starting from A/B parity `parity` on the
+// private capture stream and instantiates them into gx[parity].
+lbm_status capture_steps(lbm_ctx *c, int parity)
+{
+    const int G = c->graph_steps;
+    hipGraphExec_t &gx = c->gx[parity];
+    if (gx || G <= 0) return LBM_OK;
+    if (!c->cap) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    const int cur = c->cur;
+    c->stream = c->cap;
+    c->cur = parity;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int t = 0; t < G; t++) dispatch(c, [&](auto l) { decltype(l)::step(c); });
+        e = hipStreamEndCapture(c->cap, &graph);
+    }
+    c->stream = user;
+    c->cur = cur;
+    if (e == hipSuccess) e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("step graph: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -768,21 +794,8 @@ lbm_status lbm_step(lbm_ctx *c, int64_t n)
         while (n >= G) {
             hipGraphExec_t &gx = c->gx[c->cur];
             if (!gx) {
-                if (!c->cap) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
-                hipStream_t user = c->stream;
-                const int cur = c->cur;
-                c->stream = c->cap;
-                hipGraph_t graph = nullptr;
-                hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
-                if (e == hipSuccess) {
-                    for (int t = 0; t < G; t++) dispatch(c, [&](auto l) { decltype(l)::step(c); });
-                    e = hipStreamEndCapture(c->cap, &graph);
-                }
-                c->stream = user;
-                c->cur = cur;
-                if (e == hipSuccess) e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
-                if (graph) (void)hipGraphDestroy(graph);
-                if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("step graph: ") + hipGetErrorString(e));
+                const lbm_status st = capture_steps(c, c->cur);
+                if (st != LBM_OK) return st;
             }
             HIPCHECK(c, hipGraphLaunch(gx, c->stream));
             if (G % 2) c->cur ^= 1;
@@ -804,6 +817,13 @@ lbm_status lbm_set_graph_steps(lbm_ctx *c, int steps_per_graph)
             g = nullptr;
         }
     c->graph_steps = steps_per_graph;
+    // capture and upload both parities now, so that no later lbm_step pays
+    // for a capture
+    for (int p = 0; p < 2 && steps_per_graph > 0; p++) {
+        const lbm_status st = capture_steps(c, p);
+        if (st != LBM_OK) return st;
+        HIPCHECK(c, hipGraphUpload(c->gx[p], c->stream));
+    }
     return LBM_OK;
 }
 
@@ -1026,6 +1046,28 @@ void batch_launch(lbm_batch *b, hipStream_t s)
     b->cur ^= 1;
 }
 
+// Captures graph_steps batch steps starting from parity `parity` into gx[parity].
+lbm_status batch_capture(lbm_batch *b, int parity)
+{
+    const int G = b->graph_steps;
+    hipGraphExec_t &gx = b->gx[parity];
+    if (gx || G <= 0) return LBM_OK;
+    if (!b->cap) BHIPCHECK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    const int cur = b->cur;
+    b->cur = parity;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int t = 0; t < G; t++) batch_launch(b, b->cap);
+        e = hipStreamEndCapture(b->cap, &graph);
+    }
+    b->cur = cur;
+    if (e == hipSuccess) e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1153,18 +1195,8 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n)
         while (n >= G) {
             hipGraphExec_t &gx = b->gx[b->cur];
             if (!gx) {
-                if (!b->cap) BHIPCHECK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
-                const int cur = b->cur;
-                hipGraph_t graph = nullptr;
-                hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-                if (e == hipSuccess) {
-                    for (int t = 0; t < G; t++) batch_launch(b, b->cap);
-                    e = hipStreamEndCapture(b->cap, &graph);
-                }
-                b->cur = cur;
-                if (e == hipSuccess) e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
-                if (graph) (void)hipGraphDestroy(graph);
-                if (e != hipSuccess) return bfail(b, LBM_EDEVICE, std::string("batch graph: ") + hipGetErrorString(e));
+                const lbm_status st = batch_capture(b, b->cur);
+                if (st != LBM_OK) return st;
             }
             BHIPCHECK(b, hipGraphLaunch(gx, b->stream));
             if (G % 2) b->cur ^= 1;
@@ -1190,6 +1222,11 @@ lbm_status lbm_batch_set_graph_steps(lbm_batch *b, int steps_per_graph)
             g = nullptr;
         }
     b->graph_steps = steps_per_graph;
+    for (int p = 0; p < 2 && steps_per_graph > 0; p++) {
+        const lbm_status st = batch_capture(b, p);
+        if (st != LBM_OK) return st;
+        BHIPCHECK(b, hipGraphUpload(b->gx[p], b->stream));
+    }
     return LBM_OK;
 }
 
