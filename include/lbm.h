@@ -307,6 +307,26 @@ lbm_status lbm_probe(lbm_ctx *ctx, int k, const lbm_box *box, double threshold, 
 lbm_status lbm_components(lbm_ctx *ctx, int k, const lbm_box *box, double threshold,
                           lbm_component *out, int max_out, int *n_out);
 
+/* Allocation-free variant of lbm_components, for callers that cannot
+ * allocate device memory (tight serving or analysis loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and ordering as
+ * lbm_components; its device scratch is a fixed array inside the library
+ * (about 32.2 MiB per device, held by every device the library runs on
+ * until the process ends), so it allocates and frees nothing.  Limits: the
+ * context's domain may hold at most LBM_COMPONENTS_STATIC_MAX_NODES nodes
+ * and the phase at most LBM_COMPONENTS_STATIC_MAX_COMPONENTS components;
+ * beyond either it returns LBM_EINVAL with the reason in lbm_last_error
+ * (the second check comes after the labelling, and *n_out is then left
+ * unchanged).  The context's device must be the current device.  It
+ * synchronises the context stream, so it cannot be captured into a graph.
+ * Every call on one device shares that device's scratch: calls that overlap
+ * on one device (two host threads, or different streams) race and must be
+ * serialised by the caller. */
+#define LBM_COMPONENTS_STATIC_MAX_NODES (1 << 22)
+#define LBM_COMPONENTS_STATIC_MAX_COMPONENTS 4096
+lbm_status lbm_components_static(lbm_ctx *ctx, int k, const lbm_box *box, double threshold,
+                                 lbm_component *out, int max_out, int *n_out);
+
 /* ------------------------------------------------------------------------
  * Surrogate: an ensemble of MLPs 4 -> hidden -> hidden -> 2 (tanh) that maps
  * the parameters of a channel run to its droplet labels.  Training (full

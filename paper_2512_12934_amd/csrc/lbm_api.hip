@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -455,6 +456,67 @@ Layout make_layout(const Canon &k, const Maps &m)
     return L;
 }
 
+// Scratch of lbm_components_static: a file-scope device array, so that the
+// entry point allocates nothing.  Each device holds its own copy for the
+// life of the process; host code uses only the device address that
+// hipGetSymbolAddress returns for it (the array's name is a host-side
+// stand-in).  Layout: lab [MAX_NODES] int, slot [MAX_NODES] int, two int
+// counters, MAX_COMPONENTS CompStat, MAX_COMPONENTS lbm_component (ordered).
+constexpr size_t SCR_LAB = 0;
+constexpr size_t SCR_SLOT = SCR_LAB + (size_t)LBM_COMPONENTS_STATIC_MAX_NODES * 4;
+constexpr size_t SCR_FLAGS = SCR_SLOT + (size_t)LBM_COMPONENTS_STATIC_MAX_NODES * 4;
+constexpr size_t SCR_STATS = SCR_FLAGS + 256;
+constexpr size_t SCR_SORTED = SCR_STATS + (size_t)LBM_COMPONENTS_STATIC_MAX_COMPONENTS * sizeof(CompStat);
+constexpr size_t SCR_BYTES = SCR_SORTED + (size_t)LBM_COMPONENTS_STATIC_MAX_COMPONENTS * sizeof(lbm_component);
+static_assert(sizeof(CompStat) % 8 == 0 && sizeof(lbm_component) % 8 == 0, "scratch record alignment");
+
+static __device__ __align__(256) unsigned char scratch[SCR_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on device dev (current), resolved once.
+std::string static_scratch_resolve(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return "device index out of range for the static scratch";
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return "";
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    g_scratch_ptr[dev] = ptr;
+    return "";
+}
+
+void *static_scratch_ptr(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
+// Orders the n component records by their smallest node index (all distinct)
+// into the caller's record layout: record i goes to the rank of its first
+// index among all n.
+__global__ __launch_bounds__(256) void k_lab_order(const CompStat *__restrict__ st, int n,
+                                                   lbm_component *__restrict__ out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long fi = st[i].first;
+    int rank = 0;
+    for (int j = 0; j < n; j++) rank += st[j].first < fi ? 1 : 0;
+    lbm_component r;
+    r.first = (int64_t)fi;
+    r.size = (int64_t)st[i].size;
+    for (int d = 0; d < 3; d++) {
+        r.lo[d] = st[i].lo[d];
+        r.hi[d] = st[i].hi[d];
+    }
+    out[rank] = r;
+}
+
 }  // namespace
 
 struct lbm_ctx {
@@ -465,6 +527,7 @@ struct lbm_ctx {
     char *ws = nullptr;
     hipStream_t stream = nullptr;
     int cur = 0;           // which array holds f(t): 0 = A, 1 = B
+    int device = 0;        // the HIP device current at creation
     int64_t steps = 0;
     double mass0[2] = {0, 0};
     bool unstable = false;
@@ -687,6 +750,19 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
     c->cfg.u0 = nullptr;
     c->ws = (char *)dev_ws;
     c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, LBM_EDEVICE, "hipGetDevice failed");
+    }
+    {
+        // resolve the device address of the allocation-free labelling
+        // scratch once per device, at set-up
+        std::string why = static_scratch_resolve(c->device);
+        if (!why.empty()) {
+            delete c;
+            return fail(nullptr, LBM_EDEVICE, why);
+        }
+    }
 
     // relaxation rates (eqs. 4-5, Sec. III A)
     Physics &ph = c->ph;
@@ -1347,6 +1423,64 @@ lbm_status lbm_components(lbm_ctx *c, int k, const lbm_box *box, double threshol
     const lbm_status r = run();
     release();
     return r;
+}
+
+lbm_status lbm_components_static(lbm_ctx *c, int k, const lbm_box *box, double threshold, lbm_component *out,
+                                 int max_out, int *n_out)
+{
+    if (!c || (k != 0 && k != 1) || !n_out || max_out < 0 || (max_out > 0 && !out))
+        return fail(c, LBM_EINVAL, "bad arguments to lbm_components_static");
+    Box3 bx{};
+    const std::string why = to_box(c, box, bx);
+    if (!why.empty()) return fail(c, LBM_EINVAL, why);
+    const int64_t N = c->L.g.N;
+    if (N > LBM_COMPONENTS_STATIC_MAX_NODES)
+        return fail(c, LBM_EINVAL, "domain has more nodes than the static labelling scratch holds (" +
+                                       std::to_string(N) + " > " + std::to_string(LBM_COMPONENTS_STATIC_MAX_NODES) + ")");
+    int dev = -1;
+    HIPCHECK(c, hipGetDevice(&dev));
+    if (dev != c->device) return fail(c, LBM_EINVAL, "the context's device is not the current device");
+    char *base = (char *)static_scratch_ptr(dev);
+    if (!base) return fail(c, LBM_EDEVICE, "static scratch not resolved on this device");
+    int *lab = (int *)(base + SCR_LAB);
+    int *slot = (int *)(base + SCR_SLOT);
+    int *flags = (int *)(base + SCR_FLAGS);
+    CompStat *st = (CompStat *)(base + SCR_STATS);
+    lbm_component *sorted = (lbm_component *)(base + SCR_SORTED);
+    const StepArgs a = step_args(c);
+    const bool d2 = c->L.dim == 2;
+    if (d2) Launcher<2>::lab_init(c->L.storage, a, k, bx, (float)threshold, lab);
+    else Launcher<3>::lab_init(c->L.storage, a, k, bx, (float)threshold, lab);
+    for (int64_t round = 0;; round++) {
+        if (round > N) return fail(c, LBM_EDEVICE, "label propagation did not converge");
+        HIPCHECK(c, hipMemsetAsync(flags, 0, 4, c->stream));
+        if (d2) Launcher<2>::lab_prop(a, lab, flags, 4);
+        else Launcher<3>::lab_prop(a, lab, flags, 4);
+        int changed = 0;
+        HIPCHECK(c, hipMemcpyAsync(&changed, flags, 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        if (!changed) break;
+    }
+    HIPCHECK(c, hipMemsetAsync(flags + 1, 0, 4, c->stream));
+    if (d2) Launcher<2>::lab_roots(a, lab, slot, flags + 1);
+    else Launcher<3>::lab_roots(a, lab, slot, flags + 1);
+    int nr = 0;
+    HIPCHECK(c, hipMemcpyAsync(&nr, flags + 1, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (nr > LBM_COMPONENTS_STATIC_MAX_COMPONENTS)
+        return fail(c, LBM_EINVAL, "more components than the static labelling scratch holds (" + std::to_string(nr) +
+                                       " > " + std::to_string(LBM_COMPONENTS_STATIC_MAX_COMPONENTS) + ")");
+    *n_out = nr;
+    if (nr == 0) return LBM_OK;
+    if (d2) Launcher<2>::lab_stats(a, lab, slot, st, nr);
+    else Launcher<3>::lab_stats(a, lab, slot, st, nr);
+    hipLaunchKernelGGL(k_lab_order, dim3((nr + 255) / 256), dim3(256), 0, c->stream, st, nr, sorted);
+    HIPCHECK(c, hipGetLastError());
+    const int nc = std::min(nr, max_out);
+    if (nc > 0)
+        HIPCHECK(c, hipMemcpyAsync(out, sorted, sizeof(lbm_component) * nc, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
 }
 
 }  // extern "C"

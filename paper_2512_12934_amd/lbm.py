@@ -112,6 +112,8 @@ def lib():
         L.lbm_components.argtypes = [vp, C.c_int, C.POINTER(Box), C.c_double, C.POINTER(Component), C.c_int,
                                      C.POINTER(C.c_int)]
         L.lbm_components.restype = C.c_int
+        L.lbm_components_static.argtypes = L.lbm_components.argtypes
+        L.lbm_components_static.restype = C.c_int
         L.lbm_batch_workspace_bytes.argtypes = [cp, C.c_int]
         L.lbm_batch_workspace_bytes.restype = C.c_size_t
         L.lbm_batch_create.argtypes = [cp, C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]
@@ -328,14 +330,15 @@ class LBM:
         box = make_box(lo, hi)
         self._check(lib().lbm_probe(self._h, int(k), C.byref(box), float(threshold), C.c_void_p(out.data_ptr())))
 
-    def components(self, k, lo, hi, threshold, max_out=4096):
+    def components(self, k, lo, hi, threshold, max_out=4096, static=False):
         """Face-connected components of {rho_k > threshold} in the box:
-        list of dicts (first node, size, bbox lo/hi), by first node."""
+        list of dicts (first node, size, bbox lo/hi), by first node.
+        ``static`` calls the allocation-free entry point."""
         box = make_box(lo, hi)
         out = (Component * max_out)()
         n = C.c_int(0)
-        self._check(lib().lbm_components(self._h, int(k), C.byref(box), float(threshold), out, int(max_out),
-                                         C.byref(n)))
+        fn = lib().lbm_components_static if static else lib().lbm_components
+        self._check(fn(self._h, int(k), C.byref(box), float(threshold), out, int(max_out), C.byref(n)))
         return [{"first": out[i].first, "size": out[i].size, "lo": tuple(out[i].lo), "hi": tuple(out[i].hi)}
                 for i in range(min(n.value, max_out))], n.value
 
