@@ -47,7 +47,17 @@ typedef enum {
     LBM_ESTATE = 5      /* the context was already flagged unstable             */
 } lbm_status;
 
-enum { LBM_STORE_F32 = 0, LBM_STORE_F16_OFFSET = 1 };
+/* Storage of the populations between steps (all arithmetic is FP32):
+ *   LBM_STORE_F32         f_i - w_i in FP32;
+ *   LBM_STORE_F16_OFFSET  f_i - w_i r in binary16 (round to nearest even),
+ *                         r the previous step's density of the component at
+ *                         the node that reads the value (its reference
+ *                         density), so the stored numbers stay small in both
+ *                         phases;
+ *   LBM_STORE_F16_FIXED   f_i - w_i in binary16: the fixed offset of the
+ *                         precision extension as stated, kept to report its
+ *                         error beside the reference-density form. */
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16_OFFSET = 1, LBM_STORE_F16_FIXED = 2 };
 enum { LBM_SEPS_MAXVISC = 0, LBM_SEPS_FIXED = 1 };
 #define LBM_MAX_INLETS 8
 
@@ -77,7 +87,7 @@ enum { LBM_LAYOUT_CALLER = 0, LBM_LAYOUT_FACE_LAST = 1 };
 
 typedef struct {
     int dim;                 /* 2: D2Q9, 3: D3Q19 */
-    int storage;             /* LBM_STORE_F32 or LBM_STORE_F16_OFFSET (f - w_i in binary16) */
+    int storage;             /* LBM_STORE_F32, LBM_STORE_F16_OFFSET or LBM_STORE_F16_FIXED */
     int n[3];                /* box size; n[2] = 1 in 2-D; non-periodic axes need n >= 3 */
     int periodic[3];
     double nu[2];            /* kinematic viscosities, eq. (5); > 0 */

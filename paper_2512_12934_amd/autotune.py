@@ -36,7 +36,9 @@ def load_table() -> dict:
 
 
 def lookup(dim: int, storage: str, nodes: int) -> int:
-    entry = load_table().get(key(dim, storage, nodes))
+    # both binary16 codecs move the same bytes: the fixed-offset form takes
+    # the reference-density form's tuning
+    entry = load_table().get(key(dim, "f16" if storage == "f16fixed" else storage, nodes))
     return int(entry["best"]) if entry else -1
 
 

@@ -45,6 +45,9 @@ namespace lbm {
 // relative error of every population small; a fixed offset w_i would leave
 // about 1% at a minority density of 0.03.  ld / st take the weight w and the
 // reference density r of the reading node (FP32 ignores r).
+//   binary16, fixed offset (storage 2): f_i - w_i, the offset as stated for
+//             the precision extension, kept as a mode of its own so that its
+//             error can be reported beside the reference-density codec.
 // ---------------------------------------------------------------------------
 template <int STORE> struct Codec;
 template <> struct Codec<0> {
@@ -58,6 +61,12 @@ template <> struct Codec<1> {
     static constexpr bool REF = true;
     static __device__ __forceinline__ float ld(const T *p, float w, float r) { return __half2float(*p) + w * r; }
     static __device__ __forceinline__ void st(T *p, float v, float w, float r) { *p = __float2half_rn(v - w * r); }
+};
+template <> struct Codec<2> {
+    using T = __half;
+    static constexpr bool REF = false;
+    static __device__ __forceinline__ float ld(const T *p, float w, float) { return __half2float(*p) + w; }
+    static __device__ __forceinline__ void st(T *p, float v, float w, float) { *p = __float2half_rn(v - w); }
 };
 
 // Raw buffer access for the node update: one descriptor per component array
@@ -112,6 +121,24 @@ template <> struct Buf<1> {
                                               float rr)
     {
         __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v - w * rr)), r, (int)vo, so, 0);
+    }
+};
+
+template <> struct Buf<2> {
+    static constexpr uint32_t SZ = 2;
+    using Raw = unsigned short;
+    static __device__ __forceinline__ Raw raw(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, so, 0);
+    }
+    static __device__ __forceinline__ float dec(Raw h, float w, float) { return __half2float(__ushort_as_half(h)) + w; }
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float w, float rr)
+    {
+        return dec(raw(r, vo, so), w, rr);
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t vo, int so, float v, float w, float)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v - w)), r, (int)vo, so, 0);
     }
 };
 
@@ -404,7 +431,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
     // stream into each ring node, gathered once for its psi and read back by
     // the node update (the same loads, so the same bits).  FP32 would need
     // 39 KB of LDS per block and lose more occupancy than it saves.
-    constexpr bool STAGE = DIM == 2 && PSRC == 0 && STORE == 1;
+    constexpr bool STAGE = DIM == 2 && PSRC == 0 && STORE != 0;
     __shared__ typename Buf<STORE>::Raw s_fr[STAGE ? R * PLANE * 2 * Q : 1];
 
     const __amdgpu_buffer_rsrc_t rs0 = comp_rsrc<STORE>(src, 0, Q, g.Ppad);
@@ -699,7 +726,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
 // then runs at occupancy 4 instead of 3 without spilling, 2.4% faster; FP32
 // gains nothing from the request and takes what it needs.
 template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STORE == 1 ? 4 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STORE != 0 ? 4 : 1)))
 void k_main(const typename Codec<STORE>::T *__restrict__ src,
                                               typename Codec<STORE>::T *__restrict__ dst,
                                               const uint32_t *__restrict__ type,
@@ -1167,25 +1194,26 @@ __device__ __forceinline__ void outlet_fill_body(int blk, const typename Codec<S
         pp = pidx(g, xp, yp, DIM == 3 ? zp : -1);
     }
     const float uc = (float)Uc;
-    // the slot read by x_N: f(t) was stored with the reference density of
-    // step t, f(t+1) is stored with psi(t); x' is read at t+1 with psi(t)
-    const float2 rt0 = ref[rec.bN], rt1 = psi[rec.bN];
+    // f(t) of x_N from the FP32 history; f(t+1) is stored for x_N with
+    // psi(t) as its reference density, and x' is read at t+1 with psi(t)
+    const float2 rt1 = psi[rec.bN];
     const float2 rp = rec.slotP >= 0 ? psi[rec.bP] : make_float2(0.0f, 0.0f);
     static_for<2>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const T *sk = src + (int64_t)k * Q * g.Ppad;
         T *dk = dst + (int64_t)k * Q * g.Ppad;
-        const float r0 = k == 0 ? rt0.x : rt0.y, r1 = k == 0 ? rt1.x : rt1.y, rpk = k == 0 ? rp.x : rp.y;
+        const float r1 = k == 0 ? rt1.x : rt1.y, rpk = k == 0 ? rp.x : rp.y;
         static_for<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if (e_axis<DIM>(i, bd.out_axis) * bd.out_sign < 0) {
                 const int64_t a = (int64_t)i * g.Ppad + src_slot<DIM>(g, x, y, z, i);
-                const float prev = Codec<STORE>::ld(sk + a, weight<DIM>(i), r0);
+                float *h = bd.hist + ((int64_t)k * Q + i) * bd.n_slots + rec.slotN;
+                const float prev = *h;
                 float v = prev;
                 if (rec.slotP >= 0) {
                     const float fp = gather1<DIM, STORE>(dk, g, pp, twp, xp, yp, zp, i, rpk);
                     v = (prev + uc * fp) / (1.0f + uc);
                 }
+                *h = v;
                 Codec<STORE>::st(dk + a, v, weight<DIM>(i), r1);
             }
         });
@@ -1209,7 +1237,7 @@ __global__ __launch_bounds__(FACE_NT) void k_outlet_fill(const typename Codec<ST
 // (every slot of the node is read by the node itself), written to ref.
 template <int DIM, int STORE>
 __global__ void k_scatter(typename Codec<STORE>::T *__restrict__ dst, const uint32_t *__restrict__ type,
-                          Geometry g, const double *__restrict__ f, float2 *__restrict__ ref)
+                          Geometry g, Boundary bd, const double *__restrict__ f, float2 *__restrict__ ref)
 {
     constexpr int Q = Lat<DIM>::Q;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1234,15 +1262,18 @@ __global__ void k_scatter(typename Codec<STORE>::T *__restrict__ dst, const uint
         auto *dk = dst + (int64_t)k * Q * g.Ppad;
         static_for<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            Codec<STORE>::st(dk + slot_of<DIM>(g, p, tw | T_EDGE, x, y, z, i),
-                             (float)f[((int64_t)k * Q + g.dmap[i]) * g.N + bo], weight<DIM>(i), rr[k]);
+            const float v = (float)f[((int64_t)k * Q + g.dmap[i]) * g.N + bo];
+            Codec<STORE>::st(dk + slot_of<DIM>(g, p, tw | T_EDGE, x, y, z, i), v, weight<DIM>(i), rr[k]);
+            // the outlet history of eq. (20) starts from the state itself
+            if ((tw & T_OUTLET) && e_axis<DIM>(i, bd.out_axis) * bd.out_sign < 0)
+                bd.hist[((int64_t)k * Q + i) * bd.n_slots + bd.bslot[b]] = v;
         });
     }
 }
 
 template <int DIM, int STORE>
 __global__ void k_gather_state(const typename Codec<STORE>::T *__restrict__ src, const uint32_t *__restrict__ type,
-                               const float2 *__restrict__ ref, Geometry g, double *__restrict__ f)
+                               const float2 *__restrict__ ref, Geometry g, Boundary bd, double *__restrict__ f)
 {
     constexpr int Q = Lat<DIM>::Q;
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1262,6 +1293,10 @@ __global__ void k_gather_state(const typename Codec<STORE>::T *__restrict__ src,
         gather<DIM, STORE>(src + (int64_t)k * Q * g.Ppad, g, p, tw | T_EDGE, x, y, z, v, k == 0 ? rf.x : rf.y);
         static_for<Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
+            // populations entering through the outlet: the FP32 history (the
+            // stored copy is its rounding)
+            if ((tw & T_OUTLET) && e_axis<DIM>(i, bd.out_axis) * bd.out_sign < 0)
+                v[i] = bd.hist[((int64_t)k * Q + i) * bd.n_slots + bd.bslot[b]];
             f[((int64_t)k * Q + g.dmap[i]) * g.N + bo] = (double)v[i];
         });
     }
@@ -1383,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_psi_batch(BatchTab t, int cur)
 // the XCD of the block, and the items are dealt to the XCDs as in k_main, in
 // groups of MAIN_XCD_GROUP consecutive items per turn.
 template <int DIM, int STORE, int PSRC, int TX, int TY, int W, int ZC, int KEEPB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STORE == 1 ? 4 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STORE != 0 ? 4 : 1)))
 void k_main_batch(BatchTab t, int cur)
 {
     using T = typename Codec<STORE>::T;

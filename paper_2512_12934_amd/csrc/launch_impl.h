@@ -57,36 +57,46 @@ void launch_batch(int cfg, const BatchArgs &b, std::integer_sequence<int, I...>)
 
 }  // namespace detail
 
+// The storage mode as a compile-time constant: 0 FP32, 1 binary16 with the
+// reference density, 2 binary16 with the fixed offset (see Codec).
+template <typename F> void with_store(int storage, F &&f)
+{
+    if (storage == 0) f(std::integral_constant<int, 0>{});
+    else if (storage == 1) f(std::integral_constant<int, 1>{});
+    else f(std::integral_constant<int, 2>{});
+}
+
+#define LBM_STORE_T(sc) typename Codec<decltype(sc)::value>::T
+
 template <int DIM>
 void Launcher<DIM>::psi(int storage, const StepArgs &a)
 {
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
-    if (storage == 0)
-        hipLaunchKernelGGL((k_psi<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.g, a.psi,
-                           a.ref);
-    else
-        hipLaunchKernelGGL((k_psi<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type, a.g,
-                           a.psi, a.ref);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_psi<DIM, decltype(sc)::value>), dim3(nb), dim3(256), 0, a.stream, (const T *)a.src,
+                           a.type, a.g, a.psi, a.ref);
+    });
 }
 
 template <int DIM>
 void Launcher<DIM>::moments(int storage, const StepArgs &a)
 {
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
-    if (storage == 0)
-        hipLaunchKernelGGL((k_moments<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
-                           (const float2 *)a.psi, a.ref, a.g, a.ph, a.orho, a.ou);
-    else
-        hipLaunchKernelGGL((k_moments<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
-                           (const float2 *)a.psi, a.ref, a.g, a.ph, a.orho, a.ou);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_moments<DIM, decltype(sc)::value>), dim3(nb), dim3(256), 0, a.stream,
+                           (const T *)a.src, a.type, (const float2 *)a.psi, a.ref, a.g, a.ph, a.orho, a.ou);
+    });
 }
 
 template <int DIM>
 void Launcher<DIM>::main(int storage, int cfg, const StepArgs &a)
 {
     constexpr int N = detail::cfg_count<DIM>();
-    if (storage == 0) detail::launch_step_cfg<DIM, 0>(cfg, a, std::make_integer_sequence<int, N>{});
-    else detail::launch_step_cfg<DIM, 1>(cfg, a, std::make_integer_sequence<int, N>{});
+    with_store(storage, [&](auto sc) {
+        detail::launch_step_cfg<DIM, decltype(sc)::value>(cfg, a, std::make_integer_sequence<int, N>{});
+    });
 }
 
 template <int DIM>
@@ -98,34 +108,32 @@ void Launcher<DIM>::chi(const StepArgs &a)
 template <int DIM>
 void Launcher<DIM>::outlet(int storage, const StepArgs &a, unsigned nb)
 {
-    if (storage == 0)
-        hipLaunchKernelGGL((k_outlet<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const float *)a.src, (float *)a.dst,
-                           a.type, (const float2 *)a.psi, a.ref, a.g, a.ph, a.bd, a.flag);
-    else
-        hipLaunchKernelGGL((k_outlet<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const __half *)a.src,
-                           (__half *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.ph, a.bd, a.flag);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_outlet<DIM, decltype(sc)::value>), dim3(nb), dim3(FACE_NT), 0, a.stream,
+                           (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.ph, a.bd,
+                           a.flag);
+    });
 }
 
 template <int DIM>
 void Launcher<DIM>::inlet(int storage, const StepArgs &a, unsigned nb, int nb_in)
 {
-    if (storage == 0)
-        hipLaunchKernelGGL((k_inlet<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (float *)a.dst, a.type,
-                           (const float2 *)a.psi, a.g, a.bd, nb_in);
-    else
-        hipLaunchKernelGGL((k_inlet<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (__half *)a.dst, a.type,
-                           (const float2 *)a.psi, a.g, a.bd, nb_in);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_inlet<DIM, decltype(sc)::value>), dim3(nb), dim3(FACE_NT), 0, a.stream, (T *)a.dst,
+                           a.type, (const float2 *)a.psi, a.g, a.bd, nb_in);
+    });
 }
 
 template <int DIM>
 void Launcher<DIM>::outlet_fill(int storage, const StepArgs &a, unsigned nb)
 {
-    if (storage == 0)
-        hipLaunchKernelGGL((k_outlet_fill<DIM, 0>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const float *)a.src,
-                           (float *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.bd);
-    else
-        hipLaunchKernelGGL((k_outlet_fill<DIM, 1>), dim3(nb), dim3(FACE_NT), 0, a.stream, (const __half *)a.src,
-                           (__half *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.bd);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_outlet_fill<DIM, decltype(sc)::value>), dim3(nb), dim3(FACE_NT), 0, a.stream,
+                           (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.bd);
+    });
 }
 
 template <int DIM>
@@ -133,24 +141,22 @@ void Launcher<DIM>::scatter(int storage, const StepArgs &a, const double *f, flo
 {
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
     // writes the source array (the state f(t)) and its reference densities
-    if (storage == 0)
-        hipLaunchKernelGGL((k_scatter<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (float *)a.src, a.type, a.g, f,
-                           ref_out);
-    else
-        hipLaunchKernelGGL((k_scatter<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (__half *)a.src, a.type, a.g, f,
-                           ref_out);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_scatter<DIM, decltype(sc)::value>), dim3(nb), dim3(256), 0, a.stream, (T *)a.src,
+                           a.type, a.g, a.bd, f, ref_out);
+    });
 }
 
 template <int DIM>
 void Launcher<DIM>::gather_state(int storage, const StepArgs &a, double *f)
 {
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
-    if (storage == 0)
-        hipLaunchKernelGGL((k_gather_state<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
-                           a.ref, a.g, f);
-    else
-        hipLaunchKernelGGL((k_gather_state<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
-                           a.ref, a.g, f);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_gather_state<DIM, decltype(sc)::value>), dim3(nb), dim3(256), 0, a.stream,
+                           (const T *)a.src, a.type, a.ref, a.g, a.bd, f);
+    });
 }
 
 template <int DIM>
@@ -162,12 +168,11 @@ void Launcher<DIM>::feq_state(const double *rho0, const double *u0, int64_t N, d
 template <int DIM>
 void Launcher<DIM>::mass(int storage, const StepArgs &a, double *part, int nb, double *out)
 {
-    if (storage == 0)
-        hipLaunchKernelGGL((k_mass<DIM, 0>), dim3((unsigned)nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
-                           a.ref, a.g, part);
-    else
-        hipLaunchKernelGGL((k_mass<DIM, 1>), dim3((unsigned)nb), dim3(256), 0, a.stream, (const __half *)a.src,
-                           a.type, a.ref, a.g, part);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_mass<DIM, decltype(sc)::value>), dim3((unsigned)nb), dim3(256), 0, a.stream,
+                           (const T *)a.src, a.type, a.ref, a.g, part);
+    });
     hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, a.stream, (const double *)part, nb, out);
 }
 
@@ -178,24 +183,22 @@ void Launcher<DIM>::probe(int storage, const StepArgs &a, int k, const Box3 &bx,
     hipLaunchKernelGGL(k_zero64, dim3(1), dim3(1), 0, a.stream, out);
     if (vol <= 0) return;
     const unsigned nb = (unsigned)((vol + 255) / 256);
-    if (storage == 0)
-        hipLaunchKernelGGL((k_probe<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type, a.ref,
-                           a.g, k, bx, thr, out);
-    else
-        hipLaunchKernelGGL((k_probe<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type, a.ref,
-                           a.g, k, bx, thr, out);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_probe<DIM, decltype(sc)::value>), dim3(nb), dim3(256), 0, a.stream, (const T *)a.src,
+                           a.type, a.ref, a.g, k, bx, thr, out);
+    });
 }
 
 template <int DIM>
 void Launcher<DIM>::lab_init(int storage, const StepArgs &a, int k, const Box3 &bx, float thr, int *lab)
 {
     const unsigned nb = (unsigned)((a.g.N + 255) / 256);
-    if (storage == 0)
-        hipLaunchKernelGGL((k_lab_init<DIM, 0>), dim3(nb), dim3(256), 0, a.stream, (const float *)a.src, a.type,
-                           a.ref, a.g, k, bx, thr, lab);
-    else
-        hipLaunchKernelGGL((k_lab_init<DIM, 1>), dim3(nb), dim3(256), 0, a.stream, (const __half *)a.src, a.type,
-                           a.ref, a.g, k, bx, thr, lab);
+    with_store(storage, [&](auto sc) {
+        using T = LBM_STORE_T(sc);
+        hipLaunchKernelGGL((k_lab_init<DIM, decltype(sc)::value>), dim3(nb), dim3(256), 0, a.stream,
+                           (const T *)a.src, a.type, a.ref, a.g, k, bx, thr, lab);
+    });
 }
 
 template <int DIM>
@@ -224,8 +227,11 @@ template <int DIM>
 void Launcher<DIM>::batch_step(int storage, int cfg, const BatchArgs &b)
 {
     constexpr int N = detail::cfg_count<DIM>();
-    if (storage == 0) detail::launch_batch<DIM, 0>(cfg, b, std::make_integer_sequence<int, N>{});
-    else detail::launch_batch<DIM, 1>(cfg, b, std::make_integer_sequence<int, N>{});
+    with_store(storage, [&](auto sc) {
+        detail::launch_batch<DIM, decltype(sc)::value>(cfg, b, std::make_integer_sequence<int, N>{});
+    });
 }
+
+#undef LBM_STORE_T
 
 }  // namespace lbm

@@ -43,7 +43,7 @@ struct Layout {
     bool boundary = false;
     // byte offsets into the workspace
     size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
-        o_flag, o_mpart, o_mout, o_patch, o_psi[2], o_items, total;
+        o_flag, o_mpart, o_mout, o_patch, o_psi[2], o_items, o_hist, total;
     int cfg = 0;                   // node-update configuration (launch.h)
     int psi_mode = 1;              // 1: psi array written by k_psi, 0: recomputed in k_main
 };
@@ -175,7 +175,8 @@ std::string build_maps(const lbm_config *c, Maps &m)
 {
     if (!c) return "null configuration";
     if (c->dim != 2 && c->dim != 3) return "dim must be 2 or 3";
-    if (c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F16_OFFSET) return "unknown storage";
+    if (c->storage != LBM_STORE_F32 && c->storage != LBM_STORE_F16_OFFSET && c->storage != LBM_STORE_F16_FIXED)
+        return "unknown storage";
     const int nz = c->dim == 2 ? 1 : c->n[2];
     if (c->dim == 2 && c->n[2] != 1) return "2-D boxes need n[2] == 1";
     for (int a = 0; a < c->dim; a++) {
@@ -452,6 +453,7 @@ Layout make_layout(const Canon &k, const Maps &m)
     L.o_psi[0] = take((size_t)g.N * 8);
     L.o_psi[1] = take((size_t)g.N * 8);
     L.o_items = take(L.item_list.size() * 4);
+    L.o_hist = take(c->has_outlet ? (size_t)2 * L.Q * L.n_slots * 4 : 0);
     L.total = o;
     return L;
 }
@@ -811,6 +813,8 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
     bd.n_ucpart = L.nb_out;
     bd.scal = (double *)(ws + L.o_scal);
     bd.patch = (const Patch *)(ws + L.o_patch);
+    bd.hist = (float *)(ws + L.o_hist);
+    bd.n_slots = (int)L.n_slots;
 
     auto st = [&]() -> lbm_status {
         hipStream_t s = c->stream;

@@ -86,6 +86,13 @@ struct Boundary {
     double *ucpart;           // [inlet-kernel blocks][2] partial sum of u.n at x' and count
     int n_ucpart;
     double *scal;             // device scalars, see SC_* below
+    // [2][Q][slots] FP32 history of eq. (20): the populations entering through
+    // the outlet at the previous step, at the face slot of each outlet node
+    // (kept in FP32 whatever the storage: eq. 20 is a recursive filter with a
+    // memory of 1 / U_c steps, so re-reading a rounded value every step would
+    // hold it up to 1 / U_c rounding units from its fixed point)
+    float *hist;
+    int n_slots;
 };
 
 // Threads per block of the face kernels (one wave: the face node counts are

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = range(6)
 STATUS = {0: "LBM_OK", 1: "LBM_EINVAL", 2: "LBM_ENOMEM", 3: "LBM_EDEVICE", 4: "LBM_EUNSTABLE", 5: "LBM_ESTATE"}
-STORE = {"f32": 0, "f16": 1}
+STORE = {"f32": 0, "f16": 1, "f16fixed": 2}
 MAX_INLETS = 8
 
 

@@ -7,9 +7,12 @@ carries an absolute error of order Q * 30 * 6e-8 * rho ~ 1e-5 rho per
 population at worst.  States are therefore compared element by element as
 max |f_gpu - f_oracle| / (rho_1 + rho_2) at the node: 1e-5 after one step,
 1e-4 after 20 steps.  After 1000 steps the fields are compared with the 1e-4 bound on
-max|rho_gpu - rho_oracle| / max|rho_oracle|; velocities with the same bound
-relative to the largest velocity of the oracle field plus an absolute floor of
-2e-7 (the FP32 resolution of the momentum sum at unit density).
+max|rho_gpu - rho_oracle| / max|rho_oracle| and on the relative L2 norm of
+the velocity error; the largest single-node velocity error, relative to the
+largest velocity, is held to 1e-4 too in flows, while the static Laplace
+droplet, whose whole velocity field is a spurious current of ~1e-3 where FP32
+rounding of the momentum sums sits near 1e-7, meets 1e-4 in L2 only (its
+max-norm bound is 2e-4).
 """
 import numpy as np
 import pytest
@@ -41,16 +44,19 @@ def _compare_state(g, s, tol=None):
     return err.max()
 
 
-def _compare_fields(g, s, tol_rho, tol_u, u_floor=2e-7):
+def _compare_fields(g, s, tol_rho, tol_u, tol_u_l2=None):
+    """Max-norm errors of rho and u relative to the largest oracle value, and
+    the relative L2 error of u (bounded by tol_u_l2, default tol_u)."""
     rg, ug = g.moments()
     ro, uo, _ = s.moments()
     fluid = g.case.solid == 0
     er = _rel(rg[:, fluid], ro[:, fluid])
     eu = np.abs(ug[:, fluid] - uo[:, fluid]).max() / max(np.abs(uo[:, fluid]).max(), 1e-30)
-    abs_u = np.abs(ug[:, fluid] - uo[:, fluid]).max()
-    print(f"  rho rel err {er:.3e}  u rel err {eu:.3e} (abs {abs_u:.3e})", flush=True)
+    eu2 = np.linalg.norm(ug[:, fluid] - uo[:, fluid]) / max(np.linalg.norm(uo[:, fluid]), 1e-30)
+    print(f"  rho rel err {er:.3e}  u rel err {eu:.3e}  u L2 rel err {eu2:.3e}", flush=True)
     assert er < tol_rho
-    assert eu < tol_u or abs_u < u_floor
+    assert eu < tol_u
+    assert eu2 < (tol_u if tol_u_l2 is None else tol_u_l2)
     return er, eu
 
 
@@ -100,13 +106,17 @@ def test_one_step_parity(name, make, layout):
     ("tjunction_800x100", lambda: cases.tjunction()),
 ])
 def test_fields_step_1000(name, make):
-    """FP32 fields within 1e-4 relative of the FP64 oracle at step 1000."""
+    """FP32 fields within 1e-4 relative of the FP64 oracle at step 1000 (the
+    static droplet's velocity in L2, see the module notes)."""
     c = make()
     g = _gpu(c)
     s = oracle.Sim(c)
     g.step(1000)
     s.step(1000)
-    _compare_fields(g, s, 1e-4, 1e-4)
+    if name.startswith("laplace"):
+        _compare_fields(g, s, 1e-4, 2e-4, tol_u_l2=1e-4)
+    else:
+        _compare_fields(g, s, 1e-4, 1e-4)
     dg, do = g.mass_flux(), s.diag()
     print("  gpu", dg, "\n  oracle", do, flush=True)
     for k in range(2):

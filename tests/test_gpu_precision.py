@@ -5,10 +5,11 @@ R = 10 .. 20.
 
 FP32 storage holds the fields to 1e-4 relative (L2 norm) at step 1000.
 binary16 storage of f - w_i r (r: the reading node's density of the previous
-step) holds the diameter and the surface tension to 1%.  A fixed offset w_i
-would not: each component is also present at the minority density 0.03
-(0.1 in the Laplace sweep), where f - w_i is close to -w_i and the 11-bit
-significand leaves a relative error near 1% on every such population."""
+step) holds the diameter and the surface tension to 1%.  The fixed offset
+f - w_i (storage "f16fixed") does not: each component is also present at the
+minority density, where f - w_i is close to -w_i and the 11-bit significand
+leaves a relative error near 1e-3 on every such population; bulk nodes round
+alike, so the error is systematic and the minority density drifts."""
 import numpy as np
 import pytest
 
@@ -46,7 +47,7 @@ def _errors():
     s = oracle.Sim(c)
     s.step(1000)
     ro, uo, _ = s.moments()
-    for storage in ("f32", "f16"):
+    for storage in ("f32", "f16", "f16fixed"):
         g = LBM(c, storage=storage)
         g.step(1000)
         rg, ug = g.moments()
@@ -57,20 +58,20 @@ def _errors():
         _, Rg = _dp_reff(rg, c)
         _, Ro = _dp_reff(ro, c)
         _cache[storage] = {"rho": er, "u": eu, "rho_l2": er2, "u_l2": eu2, "D": abs(Rg - Ro) / Ro}
-    pts = {"oracle": [], "f32": [], "f16": []}
+    pts = {"oracle": [], "f32": [], "f16": [], "f16fixed": []}
     for R in (10, 12, 14, 16, 18, 20):
         c = cases.laplace(R=R, major=0.93, minor=0.1)
         s = oracle.Sim(c)
         s.step(2000)
         pts["oracle"].append(_dp_reff(s.moments()[0], c))
-        for storage in ("f32", "f16"):
+        for storage in ("f32", "f16", "f16fixed"):
             g = LBM(c, storage=storage)
             g.step(2000)
             pts[storage].append(_dp_reff(g.moments()[0], c))
     gam = {k: _gamma(v) for k, v in pts.items()}
-    for storage in ("f32", "f16"):
+    for storage in ("f32", "f16", "f16fixed"):
         _cache[storage]["gamma"] = abs(gam[storage] - gam["oracle"]) / gam["oracle"]
-    for storage in ("f32", "f16"):
+    for storage in ("f32", "f16", "f16fixed"):
         e = _cache[storage]
         print(f"  {storage}: max-norm rho {e['rho']:.2e} u {e['u']:.2e}; L2 rho {e['rho_l2']:.2e} u {e['u_l2']:.2e}; "
               f"diameter {e['D']:.2e}  gamma {e['gamma']:.2e}", flush=True)
@@ -92,3 +93,38 @@ def test_fp16_offset_meets_one_percent():
     assert e["D"] < 0.01 and e["gamma"] < 0.01
     # the fields themselves stay close as well
     assert e["rho_l2"] < 1e-3 and e["u_l2"] < 1e-2
+
+
+def test_fp16_fixed_offset_reported():
+    """The fixed offset f - w_i in binary16, as the precision extension states
+    it, measured on the same quantities: its errors are reported here and it
+    is far less accurate than the reference-density offset (at least ten
+    times the field error), which is why that offset is the binary16 mode the
+    benchmark and the batches use."""
+    e = _errors()
+    fx, rf = e["f16fixed"], e["f16"]
+    assert np.isfinite([fx["rho_l2"], fx["u_l2"], fx["D"], fx["gamma"]]).all()
+    assert fx["rho_l2"] > 10 * rf["rho_l2"]
+
+
+def test_fp16_fixed_offset_drifts_in_the_coflow_device():
+    """On the 1/4-scale co-flow device at step 1000 the fixed offset moves the
+    densities by far more than 1% of the oracle's, while the reference-density
+    offset stays within 1e-3 (measured 3e-4)."""
+    from paper_2512_12934_amd.lbm import LBM
+    c = cases.coflow3d_quarter()
+    s = oracle.Sim(c)
+    s.step(1000)
+    ro, _, _ = s.moments()
+    fluid = c.solid == 0
+    err = {}
+    for storage in ("f16", "f16fixed"):
+        print(f"[gpu] coflow quarter 1000 steps storage={storage}", flush=True)
+        g = LBM(c, storage=storage)
+        g.step(1000)
+        rg, _ = g.moments()
+        err[storage] = float(np.abs(rg[:, fluid] - ro[:, fluid]).max() / np.abs(ro[:, fluid]).max())
+    print(f"  rho max-norm relative error at step 1000: f16 {err['f16']:.2e}, f16fixed {err['f16fixed']:.2e}",
+          flush=True)
+    assert err["f16"] < 1e-3
+    assert err["f16fixed"] > 1e-2
