@@ -83,6 +83,7 @@ def lib():
         L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
         L.orc_nodes.argtypes = [C.c_void_p]
         L.orc_nodes.restype = C.c_int64
+        L.orc_set_wall_velocity.argtypes = [C.c_void_p, _dp]
         L.orc_set_next.argtypes = [C.c_void_p, _dp]
         L.orc_get_next.argtypes = [C.c_void_p, _dp]
         L.orc_set_force.argtypes = [C.c_void_p, _dp]
@@ -218,6 +219,11 @@ class Sim:
         self._keep = (solid, rho0, u0)
         self._h = lib().orc_create(C.byref(self._p), solid.ctypes.data_as(C.c_void_p),
                                    _ptr(rho0), None if u0 is None else _ptr(u0))
+        uw = getattr(case, "wall_u", None)
+        if uw is not None:
+            uw = _f64(uw).reshape(-1)
+            assert uw.size == 3 * self.N
+            lib().orc_set_wall_velocity(self._h, _ptr(uw))
 
     def close(self):
         if self._h:

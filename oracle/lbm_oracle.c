@@ -331,6 +331,7 @@ struct orc_sim {
     double *F;           /* [2][3][N] */
     double *u;           /* [3][N] common velocity (eqs. 7-8) */
     double *uc;          /* [3][N] velocity used in the collision */
+    double *uw;          /* [3][N] wall velocity of solid nodes, or NULL */
     orc_diag diag;
 };
 
@@ -555,8 +556,15 @@ static void stage_collide_stream(orc_sim *s)
             for (int i = 0; i < Q; i++) {
                 int64_t m = stream_target(s, c, s->e[i]);
                 if (m < 0) continue;                    /* leaves through an open face */
-                if (s->solid[m]) s->fn[FI(s, k, s->opp[i], n)] = fs[i];  /* eq. (B1) */
-                else s->fn[FI(s, k, i, m)] = fs[i];    /* eq. (2) */
+                if (s->solid[m]) {
+                    /* eq. (B1); a moving wall adds -2 w_i rho_k (e_i . u_w) / cs^2 */
+                    double mw = 0.0;
+                    if (s->uw)
+                        for (int d = 0; d < 3; d++) mw += s->e[i][d] * s->uw[d * N + m];
+                    s->fn[FI(s, k, s->opp[i], n)] = fs[i] - 2.0 * s->w[i] * s->rho[k * N + n] * mw / CS2;
+                } else {
+                    s->fn[FI(s, k, i, m)] = fs[i];      /* eq. (2) */
+                }
             }
         }
     }
@@ -791,7 +799,7 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     free(s->solid); free(s->inlet_of); free(s->is_outlet);
     free(s->f); free(s->fn); free(s->rho); free(s->psi);
-    free(s->F); free(s->u); free(s->uc);
+    free(s->F); free(s->u); free(s->uc); free(s->uw);
     free(s);
 }
 
@@ -830,6 +838,15 @@ void orc_moments(orc_sim *s, double *rho, double *u, double *F)
 }
 
 void orc_diagnostics(orc_sim *s, orc_diag *d) { *d = s->diag; }
+
+void orc_set_wall_velocity(orc_sim *s, const double *uw)
+{
+    free(s->uw);
+    s->uw = NULL;
+    if (!uw) return;
+    s->uw = (double *)malloc(sizeof(double) * 3 * (size_t)s->N);
+    memcpy(s->uw, uw, sizeof(double) * 3 * (size_t)s->N);
+}
 
 void orc_set_next(orc_sim *s, const double *fn)
 {

@@ -96,6 +96,14 @@ void orc_collide_node(int dim, const double *s, const double *f, double rho,
 /* Force stencil: returns the number of neighbours; off [K][3], w [K]. */
 int  orc_stencil(int dim, int *off, double *w);
 
+/* Moving walls: uw [3][N] is the velocity of every solid node (ignored on
+ * fluid nodes); NULL makes every wall rest again.  A population bounced back
+ * from a solid node s at the fluid node x picks up the wall's momentum,
+ * f_ibar(x, t+1) = f*_i(x) - 2 w_i rho_k(x) (e_i . u_w(s)) / cs^2
+ * (halfway bounce-back with a moving wall, Ladd; rho_k is the component's
+ * density at x).  Copied. */
+void orc_set_wall_velocity(orc_sim *s, const double *uw);
+
 /* ---- OpenMP threads of the node loops (timing only) ---- */
 int  orc_threads(void);
 void orc_set_threads(int n);

@@ -35,6 +35,7 @@ class Case:
     Fb: tuple = (0.0, 0.0, 0.0)
     inlets: list = dataclasses.field(default_factory=list)
     outlet: Optional[dict] = None
+    wall_u: Optional[np.ndarray] = None   # [3, N] velocity of solid nodes (moving walls)
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -251,6 +252,67 @@ def poiseuille(M: float, Fb: float, width: int = 100, a: float = 25.0, nx: int =
 
 
 # ---------------------------------------------------------------------------
+# Sheared layers between moving plates (Couette flow, Taylor deformation)
+# ---------------------------------------------------------------------------
+
+def _plates(c: Case, U_top: float, U_bot: float) -> None:
+    """Solid rows y = 0 and y = n1 - 1, moving along x at U_bot and U_top."""
+    x, y, z = c.grid()
+    top, bot = y == c.n[1] - 1, y == 0
+    c.solid = (top | bot).astype(np.uint8)
+    uw = np.zeros((3, c.N))
+    uw[0][top] = U_top
+    uw[0][bot] = U_bot
+    c.wall_u = uw
+
+
+def couette(width: int = 20, nx: int = 6, U_top: float = 0.02, U_bot: float = -0.01, nu=(0.1, 0.1),
+            rho=(0.4, 0.6), dim: int = 2, G12: float = 0.0) -> Case:
+    """Uniform two-component mixture between plates moving along x (periodic
+    along x, and z in 3-D): ``width`` fluid rows.  With no interaction the
+    steady state is the linear Couette profile between the wall planes half
+    a node outside the first and last fluid rows."""
+    ny = width + 2
+    nz = 1 if dim == 2 else 4
+    N = nx * ny * nz
+    c = Case("couette", dim, (nx, ny, nz), (True, False, True), tuple(nu), G12,
+             solid=np.zeros(N, np.uint8), rho0=None)
+    _plates(c, U_top, U_bot)
+    c.rho0 = np.stack([np.full(N, rho[0]), np.full(N, rho[1])])
+    c.meta.update(U_top=U_top, U_bot=U_bot, width=width)
+    return c
+
+
+def taylor(M: float, Ca: float, nx: int = 200, H: int = 100, R: float = 25.0, nu_c: float = 1.0 / 6.0,
+           gamma: float = None, dim: int = 2, s_eps_policy: int = 0, G12: float = 0.9,
+           major: float = COEX_G09[0], minor: float = COEX_G09[1]) -> Case:
+    """Taylor deformation (Sec. III A, Fig. 4): a droplet of component 1
+    (viscosity M nu_c) of radius R centred between two plates H fluid rows
+    apart that move along x at +U (top) and -U (bottom); periodic along x
+    (and z in 3-D, where the box is nx x (H+2) x nx/2... see ``nz``).  The
+    plate speed follows the paper's capillary number Ca = U nu_c rho_c /
+    gamma, with gamma the interfacial tension of G12 = 0.9 (GAMMA_G09)."""
+    gamma = GAMMA_G09 if gamma is None else gamma
+    ny = H + 2
+    nz = 1 if dim == 2 else max(4, int(2 * R + 12))
+    U = Ca * gamma / (nu_c * major)
+    N = nx * ny * nz
+    c = Case("taylor", dim, (nx, ny, nz), (True, False, True), (M * nu_c, nu_c), G12,
+             solid=np.zeros(N, np.uint8), rho0=None, s_eps_policy=s_eps_policy)
+    _plates(c, U, -U)
+    x, y, z = c.grid()
+    r2 = (x - nx / 2) ** 2 + (y - ny / 2) ** 2 + ((z - nz / 2) ** 2 if dim == 3 else 0)
+    c.rho0 = _rho_from_mask(r2 < R * R, major, minor)
+    # the initial velocity: the linear shear between the plates
+    u0 = np.zeros((3, N))
+    u0[0] = U * (2.0 * (y - 0.5) / H - 1.0)
+    u0[:, c.solid == 1] = 0.0
+    c.u0 = u0
+    c.meta.update(M=M, Ca=Ca, U=U, H=H, R=R, major=major, minor=minor)
+    return c
+
+
+# ---------------------------------------------------------------------------
 # Straight channel with inlet and outlet (2-D or 3-D)
 # ---------------------------------------------------------------------------
 
@@ -396,6 +458,8 @@ def transpose(case: Case, axes) -> Case:
     if case.u0 is not None:
         c.u0 = np.stack([field(case.u0[a]) for a in axes])
     c.Fb = tuple(case.Fb[a] for a in axes)
+    if case.wall_u is not None:
+        c.wall_u = np.stack([field(case.wall_u[a]) for a in axes])
     c.inlets = [face(p) for p in case.inlets]
     c.outlet = face(case.outlet) if case.outlet is not None else None
     return c

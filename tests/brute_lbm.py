@@ -117,6 +117,8 @@ class Brute:
         offs = [(dx, dy, dz) for dz in (r if self.dim == 3 else [0]) for dy in r for dx in r]
         self.stencil = [(o, float(W[o[0] ** 2 + o[1] ** 2 + o[2] ** 2])) for o in offs
                         if o[0] ** 2 + o[1] ** 2 + o[2] ** 2 in W]
+        uw = getattr(case, "wall_u", None)
+        self.uw = None if uw is None else np.asarray(uw, float).reshape((3,) + self.shape)
         rho0 = np.asarray(case.rho0, float).reshape((2,) + self.shape)
         u0 = np.zeros((3,) + self.shape) if case.u0 is None else np.asarray(case.u0, float).reshape((3,) + self.shape)
         self.f = np.stack([feq(self.e, self.w, rho0[k], u0) for k in range(2)])
@@ -253,7 +255,12 @@ class Brute:
             pulled = self._shift(fs[:, i], src3, np.nan)
             src_solid = self._shift(self.solid, src3, False)
             src_out = self._shift(np.zeros(self.shape, bool), src3, True)
-            v = np.where(src_solid & ~src_out, fs[:, self.opp[i]], pulled)
+            bounced = fs[:, self.opp[i]]
+            if self.uw is not None:
+                # a moving wall at the source adds 2 w_i rho_k (e_i . u_w) / cs^2
+                uws = self._shift(self.uw, src3, 0.0)
+                bounced = bounced + 2 * w[i] * rho * np.einsum("d,d...->...", ef[i], uws)[None] / CS2
+            v = np.where(src_solid & ~src_out, bounced, pulled)
             v = np.where(src_out, np.nan, v)
             fn[:, i] = np.where(fl, v, np.nan)
         # stage 7: inlets (eq. 13/14, then eqs. 15-19)

@@ -30,6 +30,8 @@ def _tiny_cases():
     seps = cases.laplace(n=12, R=4, nu=(0.5, 0.05), major=0.93, minor=0.1)
     out["laplace_maxvisc"] = seps
     out["laplace_fixed"] = seps.copy(s_eps_policy=1)
+    out["taylor2d"] = cases.taylor(30, 0.1, nx=14, H=10, R=3.5, nu_c=0.1)
+    out["taylor3d"] = cases.taylor(5, 0.1, nx=8, H=6, R=2.5, nu_c=0.1, dim=3)
     return out
 
 

@@ -198,6 +198,31 @@ def test_poiseuille_two_phase(M, Fb, steps):
     assert err < 0.01
 
 
+# ------------------------------------------------------------ moving walls
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_couette_profile_exact(dim):
+    """Halfway bounce-back from a moving wall (Ladd's momentum term,
+    -2 w_i rho (e_i . u_w) / cs^2) reproduces plane Couette flow exactly: the
+    steady profile between plates moving at U_bot and U_top is the straight
+    line through the wall planes half a node outside the outer fluid rows,
+    at any relaxation rate.  A wrong sign or factor in the wall term, or the
+    total instead of the component density, tilts or shifts the line.  With
+    unequal component viscosities the mixture stress is still uniform and the
+    line still holds (to the slow interdiffusion of the two relaxations)."""
+    for nu, tol in (((0.1, 0.1), 1e-13), ((0.5, 0.5), 1e-13), ((0.05, 0.3), 1e-6)):
+        c = cases.couette(nu=nu, dim=dim)
+        s = oracle.Sim(c)
+        s.step(20000)
+        rho, u, _ = s.moments()
+        ny, nx = c.n[1], c.n[0]
+        prof = u[0].reshape(-1, ny, nx)[0, :, 0]
+        y = np.arange(ny)
+        ua = c.meta["U_bot"] + (c.meta["U_top"] - c.meta["U_bot"]) * (y - 0.5) / (ny - 2)
+        assert np.abs(prof[1:-1] - ua[1:-1]).max() < tol, nu
+        assert np.abs(u[1]).max() < 1e-13
+
+
 # ------------------------------------------------------------ open boundaries
 
 def _uniform_flow_case(dim, axis, u_n, rho=(0.3, 0.7)):
