@@ -113,6 +113,15 @@ typedef struct {
                                 non-periodic face must belong to a patch */
     const double *rho0;      /* [2][N] initial component densities (> 0 on fluid) */
     const double *u0;        /* [3][N] initial velocity, or NULL for rest */
+    const double *wall_u;    /* [3][N] velocity of every solid node (moving
+                                walls, read on solid nodes only), or NULL for
+                                resting walls.  A population bounced back from
+                                a moving solid node s at the fluid node x
+                                gains -2 w_i rho_k(x) (e_i . u_w(s)) / cs^2
+                                (halfway bounce-back with a moving wall, as
+                                the sheared plates of the Taylor deformation
+                                test of Sec. III A need).  Not supported next
+                                to the outlet column (LBM_EINVAL). */
 } lbm_config;
 
 /* FP64 diagnostics of the most recent step (device-side reductions). */

@@ -694,8 +694,13 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     else return s_psi[base[2 + ey] + CEN + ex];
                 };
                 float fo[Q];
+                // a moving wall: the populations that bounce back from it take
+                // its momentum, -2 w_j rho_k (e_j . u_w) / cs^2, stored with
+                // them (only this node reads them)
+                const float *cw = (tw & T_MOVWALL) ? bd.wallc + (int64_t)bd.bslot[b] * Q : nullptr;
                 const Rates ra = {ph.se[0], ph.seps[0], ph.sq, ph.snu[0]};
                 collide_pairs<DIM, STORE == 0>(qa, r1, J1, u, F1, ra, fo);
+                if (cw) static_for<Q>([&](auto ic) { fo[decltype(ic)::value] = fmaf(cw[decltype(ic)::value], r1, fo[decltype(ic)::value]); });
                 static_for<Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     float rd = 0.0f;
@@ -709,6 +714,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                 }
                 const Rates rb = {ph.se[1], ph.seps[1], ph.sq, ph.snu[1]};
                 collide_pairs<DIM, STORE == 0>(qb, r2, J2, u, F2, rb, fo);
+                if (cw) static_for<Q>([&](auto ic) { fo[decltype(ic)::value] = fmaf(cw[decltype(ic)::value], r2, fo[decltype(ic)::value]); });
                 static_for<Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     float rd = 0.0f;

@@ -43,7 +43,8 @@ struct Layout {
     bool boundary = false;
     // byte offsets into the workspace
     size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
-        o_flag, o_mpart, o_mout, o_patch, o_psi[2], o_items, o_hist, total;
+        o_flag, o_mpart, o_mout, o_patch, o_psi[2], o_items, o_hist, o_wallc, total;
+    bool moving = false;
     int cfg = 0;                   // node-update configuration (launch.h)
     int psi_mode = 1;              // 1: psi array written by k_psi, 0: recomputed in k_main
 };
@@ -52,6 +53,8 @@ struct Layout {
 struct Maps {
     std::vector<uint32_t> type;
     std::vector<int32_t> bslot;
+    std::vector<std::vector<float>> wallc;   // [N] moving-wall term per stored direction (empty: none)
+    bool moving = false;
     std::vector<InletRec> in;
     std::vector<OutletRec> out;
     int n_xp = 0;                  // fluid x_{N-1} nodes (slots n_in .. n_in + n_xp)
@@ -107,6 +110,7 @@ struct Canon {
     lbm_config c{};
     int ax[3] = {0, 1, 2};         // memory axis a holds the caller's axis ax[a]
     std::vector<uint8_t> solid;
+    std::vector<double> wall_u;    // [3][N] in the memory frame, when permuted
 };
 
 std::string canonicalize(const lbm_config *in, Canon &k)
@@ -154,15 +158,23 @@ std::string canonicalize(const lbm_config *in, Canon &k)
     if (c.has_outlet) remap_face(c.outlet.axis, c.outlet.lo, c.outlet.hi);
     if (k.ax[0] == 0 && k.ax[1] == 1 && k.ax[2] == 2) {
         c.solid = in->solid;
+        c.wall_u = in->wall_u;
     } else {
         k.solid.resize(N);
+        if (in->wall_u) k.wall_u.resize((size_t)3 * N);
         const int64_t st[3] = {1, in->n[0], (int64_t)in->n[0] * in->n[1]};
         const int64_t os[3] = {st[k.ax[0]], st[k.ax[1]], st[k.ax[2]]};
         int64_t b = 0;
         for (int z = 0; z < c.n[2]; z++)
             for (int y = 0; y < c.n[1]; y++)
-                for (int x = 0; x < c.n[0]; x++, b++) k.solid[b] = in->solid[x * os[0] + y * os[1] + z * os[2]];
+                for (int x = 0; x < c.n[0]; x++, b++) {
+                    const int64_t ob = x * os[0] + y * os[1] + z * os[2];
+                    k.solid[b] = in->solid[ob];
+                    if (in->wall_u)
+                        for (int a = 0; a < 3; a++) k.wall_u[(size_t)a * N + b] = in->wall_u[(size_t)k.ax[a] * N + ob];
+                }
         c.solid = k.solid.data();
+        c.wall_u = in->wall_u ? k.wall_u.data() : nullptr;
     }
     // rho0 / u0 stay in the caller's frame: the initial state is built there
     // and scattered through the frame map
@@ -211,6 +223,8 @@ std::string build_maps(const lbm_config *c, Maps &m)
     }
     m.type.assign(N, 0);
     m.bslot.assign(N, -1);
+    m.wallc.assign(c->wall_u ? N : 0, std::vector<float>());
+    m.moving = false;
     m.in.clear();
     m.out.clear();
     auto solid_at = [&](const int *p) -> bool {
@@ -264,8 +278,27 @@ std::string build_maps(const lbm_config *c, Maps &m)
                 if (!ok) return "a fluid node on a non-periodic face is not covered by an inlet or the outlet";
                 continue;
             }
-            if (c->solid[(int64_t)s[0] + (int64_t)c->n[0] * ((int64_t)s[1] + (int64_t)c->n[1] * s[2])])
+            const int64_t sb = (int64_t)s[0] + (int64_t)c->n[0] * ((int64_t)s[1] + (int64_t)c->n[1] * s[2]);
+            if (c->solid[sb]) {
                 tw |= 1u << i;
+                if (c->wall_u) {
+                    // population i comes back from the solid node s = x - e_i
+                    // as the stored direction OPP[i] (= x + e_OPP[i]); a
+                    // moving s adds -2 w (e_OPP[i] . u_w) / cs^2 times rho_k
+                    double eu = 0.0;
+                    for (int a = 0; a < c->dim; a++) eu += (double)e[a] * c->wall_u[(size_t)a * N + sb];
+                    if (eu != 0.0) {
+                        auto &wc = m.wallc[b];
+                        if (wc.empty()) wc.assign(Q, 0.0f);
+                        const int j = c->dim == 2 ? Lat<2>::OPP[i] : Lat<3>::OPP[i];
+                        wc[j] = (float)(6.0 * (double)(c->dim == 2 ? weight<2>(i) : weight<3>(i)) * eu);
+                    }
+                }
+            }
+        }
+        if (c->wall_u && !m.wallc[b].empty()) {
+            tw |= T_MOVWALL;
+            m.moving = true;
         }
         const int zr = c->dim == 3 ? 2 : 0;
         bool near = false;
@@ -331,7 +364,10 @@ std::string build_maps(const lbm_config *c, Maps &m)
             m.n_xp++;
         }
     for (int64_t b = 0; b < N; b++)
-        if ((m.type[b] & T_ROLE) && m.bslot[b] < 0) m.bslot[b] = slot++;
+        if ((m.type[b] & (T_ROLE | T_MOVWALL)) && m.bslot[b] < 0) m.bslot[b] = slot++;
+    for (int64_t b = 0; b < N; b++)
+        if ((m.type[b] & T_MOVWALL) && (m.type[b] & T_OUTLET))
+            return "a moving wall next to the outlet column is not supported";
     for (auto &r : m.in) {
         r.slot1 = m.bslot[r.b1];
         r.slot2 = c->solid[r.b2] ? r.slot1 : m.bslot[r.b2];
@@ -428,6 +464,7 @@ Layout make_layout(const Canon &k, const Maps &m)
     L.n_out = (int64_t)m.out.size();
     L.n_slots = 0;
     for (auto s : m.bslot) L.n_slots = std::max<int64_t>(L.n_slots, s + 1);
+    L.moving = m.moving;
     L.boundary = L.n_in > 0 || c->has_outlet;
     L.nb_in = (int)((L.n_in + FACE_NT - 1) / FACE_NT);
     L.nb_out = (int)((L.n_out + FACE_NT - 1) / FACE_NT);
@@ -454,6 +491,7 @@ Layout make_layout(const Canon &k, const Maps &m)
     L.o_psi[1] = take((size_t)g.N * 8);
     L.o_items = take(L.item_list.size() * 4);
     L.o_hist = take(c->has_outlet ? (size_t)2 * L.Q * L.n_slots * 4 : 0);
+    L.o_wallc = take(m.moving ? (size_t)L.Q * L.n_slots * 4 : 0);
     L.total = o;
     return L;
 }
@@ -750,6 +788,7 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
     c->cfg.solid = nullptr;
     c->cfg.rho0 = nullptr;
     c->cfg.u0 = nullptr;
+    c->cfg.wall_u = nullptr;
     c->ws = (char *)dev_ws;
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess) {
@@ -815,6 +854,7 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
     bd.patch = (const Patch *)(ws + L.o_patch);
     bd.hist = (float *)(ws + L.o_hist);
     bd.n_slots = (int)L.n_slots;
+    bd.wallc = L.moving ? (const float *)(ws + L.o_wallc) : nullptr;
 
     auto st = [&]() -> lbm_status {
         hipStream_t s = c->stream;
@@ -826,6 +866,14 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
         if (L.n_out)
             HIPCHECK(c, hipMemcpyAsync(ws + L.o_out, m.out.data(), m.out.size() * sizeof(OutletRec), hipMemcpyHostToDevice, s));
         HIPCHECK(c, hipMemcpyAsync(ws + L.o_patch, patches, sizeof patches, hipMemcpyHostToDevice, s));
+        std::vector<float> wallc;
+        if (L.moving) {
+            wallc.assign((size_t)L.n_slots * L.Q, 0.0f);
+            for (int64_t b = 0; b < L.g.N; b++)
+                if (!m.wallc[b].empty())
+                    for (int j = 0; j < L.Q; j++) wallc[(size_t)m.bslot[b] * L.Q + j] = m.wallc[b][j];
+            HIPCHECK(c, hipMemcpyAsync(ws + L.o_wallc, wallc.data(), wallc.size() * 4, hipMemcpyHostToDevice, s));
+        }
         if (!L.item_list.empty())
             HIPCHECK(c, hipMemcpyAsync(ws + L.o_items, L.item_list.data(), L.item_list.size() * 4,
                                        hipMemcpyHostToDevice, s));

@@ -17,6 +17,7 @@ enum : uint32_t {
     T_X2 = 1u << 25,            // x2: neighbour of an inlet node
     T_PATCH_SHIFT = 26,         // 3 bits: inlet patch of an x1 / x2 node
     T_PATCH_MASK = 7u << 26,
+    T_MOVWALL = 1u << 29,       // a bounce-back link of this node meets a moving wall
     T_ROLE = T_INLET | T_OUTLET | T_XPRIME | T_X2,
 };
 
@@ -93,6 +94,10 @@ struct Boundary {
     // hold it up to 1 / U_c rounding units from its fixed point)
     float *hist;
     int n_slots;
+    // [slots][Q] moving-wall term per stored direction j of a T_MOVWALL node,
+    // to be multiplied by the component's density: -2 w_j (e_j . u_w) / cs^2
+    // where x + e_j is a moving solid node, 0 elsewhere
+    const float *wallc;
 };
 
 // Threads per block of the face kernels (one wave: the face node counts are

@@ -42,7 +42,8 @@ class Config(C.Structure):
                 ("G12", C.c_double), ("Gw", C.c_double * 2), ("Fb", C.c_double * 3),
                 ("n_inlets", C.c_int), ("inlets", Inlet * MAX_INLETS), ("has_outlet", C.c_int),
                 ("outlet", Outlet), ("tile_config", C.c_int), ("layout", C.c_int),
-                ("solid", C.c_void_p), ("rho0", C.c_void_p), ("u0", C.c_void_p)]
+                ("solid", C.c_void_p), ("rho0", C.c_void_p), ("u0", C.c_void_p),
+                ("wall_u", C.c_void_p)]
 
 
 class Box(C.Structure):
@@ -175,10 +176,13 @@ def make_config(case, storage="f32", tile_config=-1, layout="caller"):
     solid = np.ascontiguousarray(case.solid, dtype=np.uint8).reshape(-1)
     rho0 = np.ascontiguousarray(case.rho0, dtype=np.float64).reshape(-1)
     u0 = None if case.u0 is None else np.ascontiguousarray(case.u0, dtype=np.float64).reshape(-1)
+    uw = getattr(case, "wall_u", None)
+    uw = None if uw is None else np.ascontiguousarray(uw, dtype=np.float64).reshape(-1)
     cfg.solid = solid.ctypes.data
     cfg.rho0 = rho0.ctypes.data
     cfg.u0 = None if u0 is None else u0.ctypes.data
-    return cfg, (solid, rho0, u0)
+    cfg.wall_u = None if uw is None else uw.ctypes.data
+    return cfg, (solid, rho0, u0, uw)
 
 
 def tile_configs(dim):

@@ -73,6 +73,10 @@ SMALL = [
     ("coflow_small_y", lambda: cases.transpose(cases.coflow3d(length=40, width=10, inner=4), (1, 0, 2))),
     ("coflow_small_z", lambda: cases.transpose(cases.coflow3d(length=40, width=10, inner=4), (1, 2, 0))),
     ("channel_nochi", lambda: cases.channel(70, 12, 0.01, droplet=(50, 7, 4), chi_on=False, alpha_on=False)),
+    # moving walls (sheared plates of the Taylor deformation test)
+    ("taylor2d", lambda: cases.taylor(30, 0.1, nx=70, H=20, R=6, nu_c=0.1)),
+    ("taylor3d", lambda: cases.taylor(5, 0.1, nx=34, H=10, R=4, nu_c=0.1, dim=3)),
+    ("couette3d_z", lambda: cases.transpose(cases.couette(dim=3, nx=8), (2, 0, 1))),
 ]
 
 
@@ -278,4 +282,21 @@ def test_degenerate_domains(dim):
         assert abs(m1[k] - m0[k]) <= 7 * q * 2.0 ** -26
     err = _compare_state(g, s)
     print(f"  single node: state err {err:.2e}", flush=True)
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_couette_steady_state(dim):
+    """Plates moving at U_bot and U_top: the FP32 steady profile is the exact
+    Couette line of the oracle's pin to FP32 resolution."""
+    c = cases.couette(dim=dim)
+    g = _gpu(c)
+    g.step(20000)
+    _, u = g.moments()
+    ny, nx = c.n[1], c.n[0]
+    prof = u[0].reshape(-1, ny, nx)[0, :, 0]
+    y = np.arange(ny)
+    ua = c.meta["U_bot"] + (c.meta["U_top"] - c.meta["U_bot"]) * (y - 0.5) / (ny - 2)
+    err = np.abs(prof[1:-1] - ua[1:-1]).max()
+    print(f"  Couette max |u - u_exact| {err:.2e}", flush=True)
     assert err < 1e-6
