@@ -73,6 +73,11 @@ SMALL = [
     ("coflow_small_y", lambda: cases.transpose(cases.coflow3d(length=40, width=10, inner=4), (1, 0, 2))),
     ("coflow_small_z", lambda: cases.transpose(cases.coflow3d(length=40, width=10, inner=4), (1, 2, 0))),
     ("channel_nochi", lambda: cases.channel(70, 12, 0.01, droplet=(50, 7, 4), chi_on=False, alpha_on=False)),
+    # droplet migration channels, corrected and original outlet
+    ("migration2d", lambda: cases.channel(90, 16, 0.02, nu=(0.17, 0.17), droplet=(70, 8.5, 5), major=0.96,
+                                          minor=0.09)),
+    ("migration3d_original", lambda: cases.channel(40, 10, 0.02, nu=(0.17, 0.17), droplet=(30, 5.5, 5.5, 3),
+                                                   major=0.96, minor=0.09, dim=3, chi_on=False)),
     # moving walls (sheared plates of the Taylor deformation test)
     ("taylor2d", lambda: cases.taylor(30, 0.1, nx=70, H=20, R=6, nu_c=0.1)),
     ("taylor3d", lambda: cases.taylor(5, 0.1, nx=34, H=10, R=4, nu_c=0.1, dim=3)),
