@@ -428,6 +428,73 @@ def coflow3d_quarter(**kw) -> Case:
     return coflow3d(length=150, width=30, inner=8, **kw)
 
 
+def coflow_cylinder(length: int = 600, R: int = 60, r_in: int = 15, t_wall: int = 7, L_cap: int = 60,
+                    focus=None, u_c: float = 0.02, u_d: float = 0.005, nu_c: float = 0.067, M: float = 5.0,
+                    G12: float = 0.9, major: float = COEX_G09[0], minor: float = COEX_G09[1],
+                    alpha_on=True, chi_on=True) -> Case:
+    """Coaxial co-flow device built from the cylinder equation (eq. 28): the
+    fluid domain of the outer tube is y'^2 + z'^2 <= R^2 (y', z' measured from
+    the tube axis), 0 <= x < length.  An inner capillary of inner radius r_in
+    and wall thickness t_wall runs from the inlet face to x = L_cap; its wall
+    (r_in < r <= r_in + t_wall) is solid.  The dispersed phase (component 1,
+    viscosity M nu_c) enters through the capillary at u_d, the continuous
+    phase through the annulus around it at u_c, and leaves through the
+    outlet face x = length - 1.
+
+    ``focus = (x0, L, R_f)`` adds the focused structure: an orifice of radius
+    R_f over x0 <= x < x0 + L downstream of the capillary tip, where the
+    outer flow is squeezed through the narrower throat.
+
+    The box is length x (2R + 3) x (2R + 3) with the tube axis at the centre
+    node, so one solid layer at least surrounds the tube.  Both inlets are
+    rectangles on the x = 0 face (later patches take precedence): the whole
+    face for the continuous phase, and the square of side 2 r_in + 1 around
+    the axis for the dispersed phase, which holds only capillary-interior
+    fluid nodes when t_wall >= (sqrt(2) - 1) r_in (its corners fall on the
+    capillary wall).  The initial state is the phase layout at the plug
+    velocity that carries the inlets' total flow through each cross-section."""
+    if t_wall < (math.sqrt(2.0) - 1.0) * r_in:
+        raise ValueError("t_wall must be at least (sqrt(2) - 1) r_in so that the square inner inlet patch "
+                         "holds only capillary-interior nodes")
+    if not (0 < r_in and r_in + t_wall < R and 2 <= L_cap < length - 2):
+        raise ValueError("the capillary must fit inside the tube and end inside the box")
+    n1 = 2 * R + 3
+    c0 = R + 1
+    c = Case("coflow_cylinder", 3, (length, n1, n1), (False, False, False), (M * nu_c, nu_c), G12,
+             solid=None, rho0=None)
+    x, y, z = c.grid()
+    r2 = (y - c0) ** 2 + (z - c0) ** 2
+    R_x = np.full(length, float(R))
+    if focus is not None:
+        x0, L, R_f = focus
+        if not (L_cap < x0 and x0 + L < length - 2 and 0 < R_f < R):
+            raise ValueError("the orifice must sit between the capillary tip and the outlet, narrower than R")
+        R_x[x0:x0 + L] = R_f
+    tube = r2 <= R_x[x] ** 2
+    cap_wall = (x < L_cap) & (r2 > r_in ** 2) & (r2 <= (r_in + t_wall) ** 2)
+    core = (x < L_cap) & (r2 <= r_in ** 2)
+    c.solid = (~tube | cap_wall).astype(np.uint8)
+    c.rho0 = _rho_from_mask(core, major, minor)
+    # plug velocity carrying the inlets' flow through each cross-section
+    face0 = (x == 0) & (c.solid == 0)
+    A_core = int((face0 & (r2 <= r_in ** 2)).sum())
+    A_ann = int(face0.sum()) - A_core
+    Q = u_c * A_ann + u_d * A_core
+    area = np.bincount(x[c.solid == 0], minlength=length).astype(float)
+    u0 = np.zeros((3, c.N))
+    u0[0] = Q / np.maximum(area[x], 1.0)
+    u0[:, c.solid == 1] = 0.0
+    c.u0 = u0
+    c.inlets = [
+        inlet(0, 0, (0, 0, 0), (1, n1, n1), (minor, major), u_c, alpha_on),
+        inlet(0, 0, (0, c0 - r_in, c0 - r_in), (1, c0 + r_in + 1, c0 + r_in + 1), (major, minor), u_d, alpha_on),
+    ]
+    c.outlet = outlet(0, 1, (0, 0, 0), (1, n1, n1), chi_on)
+    c.meta.update(R=R, r_in=r_in, t_wall=t_wall, L_cap=L_cap, focus=focus, u_c=u_c, u_d=u_d, M=M,
+                  A_core=A_core, A_annulus=A_ann, width=2 * R + 1, inner=2 * r_in + 1)
+    return c
+
+
 def transpose(case: Case, axes) -> Case:
     """The same case with its lattice axes reordered: axis a of the result is
     axis ``axes[a]`` of ``case`` (a 3-D permutation).  Arrays, patches, the

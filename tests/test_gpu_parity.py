@@ -78,6 +78,8 @@ SMALL = [
                                           minor=0.09)),
     ("migration3d_original", lambda: cases.channel(40, 10, 0.02, nu=(0.17, 0.17), droplet=(30, 5.5, 5.5, 3),
                                                    major=0.96, minor=0.09, dim=3, chi_on=False)),
+    # the cylindrical co-flow device (eq. 28) with its capillary and a focusing orifice
+    ("cylinder_focus", lambda: cases.coflow_cylinder(length=40, R=6, r_in=2, t_wall=1, L_cap=10, focus=(18, 5, 4))),
     # moving walls (sheared plates of the Taylor deformation test)
     ("taylor2d", lambda: cases.taylor(30, 0.1, nx=70, H=20, R=6, nu_c=0.1)),
     ("taylor3d", lambda: cases.taylor(5, 0.1, nx=34, H=10, R=4, nu_c=0.1, dim=3)),
@@ -135,6 +137,19 @@ def test_fields_step_1000(name, make):
 def test_coflow_quarter_step_1000():
     """The 1/4-scale co-flow device (150 x 30 x 30 fluid, D3Q19) at step 1000."""
     c = cases.coflow3d_quarter()
+    g = _gpu(c)
+    s = oracle.Sim(c)
+    g.step(1000)
+    s.step(1000)
+    _compare_fields(g, s, 1e-4, 1e-4)
+
+
+@pytest.mark.parametrize("focus", [None, (40, 10, 10)])
+def test_cylinder_quarter_step_1000(focus):
+    """The cylindrical co-flow device at 1/4 scale (150 long, tube radius 15,
+    capillary radius 4 with a 2-node wall, 15 long; optionally a focusing
+    orifice of radius 10) at step 1000."""
+    c = cases.coflow_cylinder(length=150, R=15, r_in=4, t_wall=2, L_cap=15, focus=focus)
     g = _gpu(c)
     s = oracle.Sim(c)
     g.step(1000)
