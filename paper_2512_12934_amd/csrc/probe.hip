@@ -3,7 +3,7 @@
 // to the published peak for the rooflines of the step kernels.
 #include <hip/hip_runtime.h>
 
-#include "../../include/lbm.h"
+#include "../../include/lbm_probe.h"
 #include "lattice.h"
 
 namespace {

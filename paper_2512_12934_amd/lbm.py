@@ -97,8 +97,6 @@ def lib():
         L.lbm_time_kernels.restype = C.c_int
         L.lbm_tile_configs.argtypes = [C.c_int]
         L.lbm_tile_configs.restype = C.c_int
-        L.lbm_stream_probe.argtypes = [vp, vp, C.c_size_t, C.c_int, C.c_int, vp, C.POINTER(C.c_double)]
-        L.lbm_stream_probe.restype = C.c_int
         L.lbm_tile_config_desc.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int)]
         L.lbm_tile_config_desc.restype = C.c_int
         L.lbm_set_graph_steps.argtypes = [vp, C.c_int]
@@ -133,6 +131,25 @@ def lib():
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
+
+
+_probe_lib = None
+PROBE_LIB_PATH = os.path.join(HERE, "libprobe.so")
+
+
+def probe_lib():
+    """The measurement library (streaming probes), separate from the solver."""
+    global _probe_lib
+    if _probe_lib is None:
+        import torch  # noqa: F401
+        if not os.path.exists(PROBE_LIB_PATH):
+            raise RuntimeError(f"{PROBE_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(PROBE_LIB_PATH)
+        vp = C.c_void_p
+        L.lbm_stream_probe.argtypes = [vp, vp, C.c_size_t, C.c_int, C.c_int, vp, C.POINTER(C.c_double)]
+        L.lbm_stream_probe.restype = C.c_int
+        _probe_lib = L
+    return _probe_lib
 
 
 LAYOUT = {"caller": 0, "face_last": 1}
@@ -205,7 +222,7 @@ def stream_probe(nbytes=1 << 30, reps=20, device="cuda:0"):
     for kind, name in enumerate(("copy_b32", "copy_b128", "read_b128", "copy_b32x8", "pull_d3q19",
                                  "pull_d3q19_ahead", "pull_d3q19_pairs")):
         r = C.c_double(0.0)
-        st = lib().lbm_stream_probe(a.data_ptr(), b.data_ptr(), nbytes, kind, reps, s.cuda_stream, C.byref(r))
+        st = probe_lib().lbm_stream_probe(a.data_ptr(), b.data_ptr(), nbytes, kind, reps, s.cuda_stream, C.byref(r))
         if st != LBM_OK:
             raise LBMError(st, "stream probe failed")
         out[name] = round(r.value, 1)

@@ -1,5 +1,7 @@
-"""The C-ABI library loads and exports every entry point of include/lbm.h;
-configuration validation (pure host code) answers without a GPU."""
+"""The C-ABI libraries load and export every entry point of their headers
+(include/lbm.h: the solver, liblbm.so; include/lbm_probe.h: the measurement
+library, libprobe.so); configuration validation (pure host code) answers
+without a GPU."""
 import ctypes as C
 import os
 import re
@@ -10,8 +12,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+def _declared(header="lbm.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     return sorted(set(re.findall(r"^\s*(?:lbm_status|size_t|void|int64_t|int|lbm_ctx|const char)\s*\*?\s*((?:lbm|surr)_\w+)\s*\(",
                                  src, re.M)))
 
@@ -30,6 +32,17 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 10
     for n in names:
         assert hasattr(lib, n), n
+    # measurement code stays out of the solver library
+    assert not hasattr(lib, "lbm_stream_probe")
+
+
+def test_probe_library_exports_its_header(lib):
+    from paper_2512_12934_amd import lbm
+    names = _declared("lbm_probe.h")
+    assert names == ["lbm_stream_probe"]
+    pl = lbm.probe_lib()
+    for n in names:
+        assert hasattr(pl, n), n
 
 
 def test_workspace_bytes_validates(lib):
@@ -117,11 +130,12 @@ def test_all_solid_box_is_valid(lib):
 def test_stream_probe_rejects_bad_arguments(lib):
     """Argument checks of the measurement hook answer before any device call
     (the pointers below are never dereferenced)."""
-    from paper_2512_12934_amd.lbm import LBM_EINVAL
+    from paper_2512_12934_amd.lbm import LBM_EINVAL, probe_lib
+    pl = probe_lib()
     r = C.c_double(0.0)
     fake = C.c_void_p(4096)
-    call = lambda nbytes, kind, reps=1: lib.lbm_stream_probe(fake, fake, C.c_size_t(nbytes), kind, reps, None,
-                                                             C.byref(r))
+    call = lambda nbytes, kind, reps=1: pl.lbm_stream_probe(fake, fake, C.c_size_t(nbytes), kind, reps, None,
+                                                            C.byref(r))
     assert call(1 << 20, 7) == LBM_EINVAL            # unknown kind
     assert call(1 << 20, -1) == LBM_EINVAL
     assert call(1 << 20, 0, reps=0) == LBM_EINVAL
@@ -129,4 +143,4 @@ def test_stream_probe_rejects_bad_arguments(lib):
     # the pull pattern needs room for 20 planes of 128 x 128 nodes x 38 populations
     assert call(38 * 4 * 128 * 128 * 19, 4) == LBM_EINVAL
     assert call(1 << 31, 5) == LBM_EINVAL            # beyond 32-bit buffer offsets
-    assert lib.lbm_stream_probe(None, fake, C.c_size_t(1 << 20), 0, 1, None, C.byref(r)) == LBM_EINVAL
+    assert pl.lbm_stream_probe(None, fake, C.c_size_t(1 << 20), 0, 1, None, C.byref(r)) == LBM_EINVAL

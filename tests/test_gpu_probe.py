@@ -16,7 +16,7 @@ D3Q19 = {(0, 0, 0)} | {(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c i
 @pytest.mark.parametrize("kind", [4, 5])
 def test_pull_probe_moves_each_population_from_its_neighbour(kind):
     import torch
-    from paper_2512_12934_amd.lbm import LBM_OK, lib
+    from paper_2512_12934_amd.lbm import LBM_OK, probe_lib as lib
     PX = PY = 128
     nz = 20
     M = nz * PX * PY
@@ -49,7 +49,7 @@ def test_pull_probe_moves_each_population_from_its_neighbour(kind):
 
 def test_pull_pairs_probe_moves_each_pair_from_its_neighbour():
     import torch
-    from paper_2512_12934_amd.lbm import LBM_OK, lib
+    from paper_2512_12934_amd.lbm import LBM_OK, probe_lib as lib
     PX = PY = 128
     nz = 20
     M = nz * PX * PY
