@@ -213,6 +213,21 @@ __device__ __forceinline__ float gather1(const typename Codec<STORE>::T *__restr
     return Codec<STORE>::ld(fk + slot_of<DIM>(g, p, tw, x, y, z, i), weight<DIM>(i), rr);
 }
 
+// Byte offset of population plane i within one component array, formed at
+// its point of use by one scalar multiply.  The copy through an empty asm
+// statement makes the stride opaque, so the compiler cannot hoist the 19
+// products out of the node loop: held there, they took 19 scalar registers,
+// the kernel ran out of them, and every access then read its offset back
+// from a vector-register lane (v_readlane) and waited five cycles before
+// the memory instruction could use it.
+template <int STORE>
+__device__ __forceinline__ int plane_bytes(const Geometry &g, int i)
+{
+    int s = (int)((uint32_t)g.Ppad * Buf<STORE>::SZ);
+    asm volatile("" : "+s"(s));
+    return s * i;
+}
+
 // Where the populations that stream into node p (pull) are stored, as byte
 // offsets within one component: a[i] per lane, plus the wave-uniform offset
 // so_i that uniform_plane() gives.  The wave takes the cheapest of three
@@ -234,7 +249,6 @@ __device__ __forceinline__ void gather_addr(const Geometry &g, uint32_t p, uint3
     constexpr uint32_t SZ = Buf<STORE>::SZ;
     const uint32_t vb = (p - 1u) * SZ;
     const uint32_t sy = (uint32_t)g.P[0] * SZ, sz = (uint32_t)g.P[0] * (uint32_t)g.P[1] * SZ;
-    const uint32_t plane = (uint32_t)g.Ppad * SZ;
     auto shifted = [&](auto ic) -> uint32_t {
         constexpr int i = decltype(ic)::value;
         constexpr int ex = Lat<DIM>::E[i][0], ey = Lat<DIM>::E[i][1], ez = Lat<DIM>::E[i][2];
@@ -250,8 +264,8 @@ __device__ __forceinline__ void gather_addr(const Geometry &g, uint32_t p, uint3
     } else if (__ballot(tw & T_EDGE) == 0) {
         static_for<Lat<DIM>::Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            const uint32_t own = p * SZ + (uint32_t)Lat<DIM>::OPP[i] * plane;
-            a[i] = ((tw >> i) & 1u) ? own : shifted(ic) + (uint32_t)i * plane;
+            const uint32_t own = p * SZ + (uint32_t)plane_bytes<STORE>(g, Lat<DIM>::OPP[i]);
+            a[i] = ((tw >> i) & 1u) ? own : shifted(ic) + (uint32_t)plane_bytes<STORE>(g, i);
         });
     } else {
         static_for<Lat<DIM>::Q>([&](auto ic) {
@@ -265,7 +279,9 @@ __device__ __forceinline__ void gather_addr(const Geometry &g, uint32_t p, uint3
 template <int STORE>
 __device__ __forceinline__ int uniform_plane(const Geometry &g, bool wave_fast, int i)
 {
-    return wave_fast ? (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ) : 0;
+    // formed unconditionally and selected, so the node loop takes no branch here
+    const int so = plane_bytes<STORE>(g, i);
+    return wave_fast ? so : 0;
 }
 
 // The stored bits of the populations that stream into node p, one component.
@@ -705,7 +721,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     constexpr int i = decltype(ic)::value;
                     float rd = 0.0f;
                     if constexpr (Codec<STORE>::REF) rd = dest_psi(ic).x;
-                    Buf<STORE>::st(rd0, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i), rd);
+                    Buf<STORE>::st(rd0, vo, plane_bytes<STORE>(g, i), fo[i], weight<DIM>(i), rd);
                 });
                 if constexpr (!KEEPB) {
                     float f[Q];
@@ -719,7 +735,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     constexpr int i = decltype(ic)::value;
                     float rd = 0.0f;
                     if constexpr (Codec<STORE>::REF) rd = dest_psi(ic).y;
-                    Buf<STORE>::st(rd1, vo, (int)((int64_t)i * g.Ppad * Buf<STORE>::SZ), fo[i], weight<DIM>(i), rd);
+                    Buf<STORE>::st(rd1, vo, plane_bytes<STORE>(g, i), fo[i], weight<DIM>(i), rd);
                 });
             }
         }
