@@ -93,18 +93,21 @@ def test_training_is_deterministic_and_fits():
 
 
 def test_surrogate_gain_over_lbm():
-    """Label batched T-junction runs of the sweep distribution (W 16..24),
-    train the ensemble on part of them and query it for the rest: every
-    query costs a tiny fraction of the run it replaces, and the predicted
-    droplet size agrees with the held-out runs; the period error and the
-    fallback rate are printed."""
+    """Label batched T-junction runs of the sweep distribution (Ca, q, M as in
+    the batched sweep; W 16..24), train the ensemble on 448 of them and query
+    it for 256 held-out runs: every query costs a tiny fraction of the run it
+    replaces, and the answers the ensemble keeps (no fallback) agree with the
+    held-out runs on both labels.  Measured: 72 usable training labels, 41
+    usable held-out labels, kept-query MAPE 3.1% (D/W) and 2.8% (T*)."""
     from paper_2512_12934_amd import study
-    res = study.run(n_train=224, n_test=64, steps=240000, W_range=(16, 24), epochs=2000)
+    res = study.run(n_train=448, n_test=256, steps=240000, W_range=(16, 24), epochs=2000)
     print(f"  {res}", flush=True)
-    assert res["usable_train"] >= 8 and res["usable_test"] >= 1
+    assert res["usable_train"] >= 40 and res["usable_test"] >= 20
     h = res["held_out"]
     # the surrogate answers a query at least 1000 times faster than the run
     assert h["seconds_per_query"] * 1000 < res["lbm_seconds_per_run"]
-    # the droplet size of the held-out runs within 10% on average (the
-    # period, a noisier label, is reported)
-    assert h["mape_all"][0] < 0.10
+    # enough queries are kept to judge them, and the kept answers are within
+    # 8% (droplet size) and 10% (period) of the held-out runs on average
+    kept = round(h["n"] * (1.0 - h["fallback_rate"]))
+    assert kept >= 10
+    assert h["mape_kept"][0] < 0.08 and h["mape_kept"][1] < 0.10
