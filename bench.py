@@ -68,15 +68,18 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary FP16, 2-D and batched measurements")
     ap.add_argument("--batch-members", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=400)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only time the batched sweep (no one-by-one comparison): a short run for profilers")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale reference for HBM counters)")
     return ap.parse_args()
 
 
-def batched(args, dev, t0, t1):
+def batched(args, dev, t0, t1, compare=True):
     """The 256-instance T-junction sweep (W 32..128, FP16-offset storage):
     one batch (one launch per stage for all members, graph-replayed) against
-    the same members stepped one context at a time."""
+    the same members stepped one context at a time (compare=False skips the
+    one-at-a-time leg)."""
     import torch
     from paper_2512_12934_amd import cases
     from paper_2512_12934_amd.lbm import Batch, lib
@@ -94,6 +97,12 @@ def batched(args, dev, t0, t1):
     t1.record(b.stream)
     torch.cuda.synchronize()
     mb = t0.elapsed_time(t1) / nb
+    if not compare:
+        del b
+        torch.cuda.empty_cache()
+        return {"members": len(cs), "fluid_nodes": fluid, "storage": "f16",
+                "batched_ms_per_step": round(mb, 4), "batched_MLUPS": round(fluid / (mb / 1e3) / 1e6, 1),
+                "create_s": round(t_create, 2)}
     # the same members, one context at a time (plain launches, as a caller
     # without the batch would run them)
     L = lib()
@@ -213,6 +222,10 @@ def main():
     from paper_2512_12934_amd.lbm import LBM
 
     dev = torch.device("cuda:0")
+    if args.batch_only:
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        print(json.dumps({"batched_sweep": batched(args, dev, t0, t1, compare=False)}), flush=True)
+        return
     # the rates plain streaming kernels reach here: the practical ceiling
     # next to the published peak
     from paper_2512_12934_amd.lbm import stream_probe
