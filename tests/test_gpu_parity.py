@@ -60,6 +60,25 @@ def _compare_fields(g, s, tol_rho, tol_u, tol_u_l2=None):
     return er, eu
 
 
+def _x2_solid(c):
+    """Part of the column behind the inlet is solid: those inlet nodes have no
+    x2 and take the prescribed equilibrium (the x2-solid branch of eq. 13)."""
+    x, y, z = c.grid()
+    c.solid = (c.solid.astype(bool) | ((x == 1) & (y >= 3) & (y <= 4))).astype(np.uint8)
+    c.name += "_x2solid"
+    return c
+
+
+def _backflow(c):
+    """The initial flow runs back through the outlet: U_c of eq. 21 is negative
+    (clamped at 0) and Q' of eq. 23 has the opposite sign of Q_in (chi left at 1)."""
+    x, _, _ = c.grid()
+    c.u0 = c.u0.copy()
+    c.u0[0][(c.solid == 0) & (x >= c.n[0] - 6)] = -0.02
+    c.name += "_backflow"
+    return c
+
+
 SMALL = [
     ("random2d", lambda: cases.random_box((70, 20), seed=1, u_amp=0.01)),
     ("random2d_walls", lambda: cases.random_box((70, 21), seed=2, periodic=(False, False, True), walls=True,
@@ -84,6 +103,11 @@ SMALL = [
     ("taylor2d", lambda: cases.taylor(30, 0.1, nx=70, H=20, R=6, nu_c=0.1)),
     ("taylor3d", lambda: cases.taylor(5, 0.1, nx=34, H=10, R=4, nu_c=0.1, dim=3)),
     ("couette3d_z", lambda: cases.transpose(cases.couette(dim=3, nx=8), (2, 0, 1))),
+    # branches of the open faces: inlet nodes whose x2 is solid, and a column
+    # flowing back through the outlet
+    ("inlet_x2_solid", lambda: _x2_solid(cases.channel(30, 10, 0.01))),
+    ("inlet_x2_solid3d", lambda: _x2_solid(cases.channel(20, 6, 0.01, dim=3))),
+    ("backflow", lambda: _backflow(cases.channel(30, 10, 0.01))),
 ]
 
 
@@ -110,6 +134,25 @@ def test_one_step_parity(name, make, layout):
     dg, do = g.mass_flux(), s.diag()
     for key in ("q_in", "q_out", "chi", "u_conv"):
         assert abs(dg[key] - do[key]) <= 1e-5 * max(1.0, abs(do[key])), key
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_backflow_clamps_uc_and_keeps_chi(dim):
+    """A column flowing back through the outlet: the GPU takes the same
+    branches as the oracle, U_c clamped at 0 (and counted) and chi left at 1
+    because Q_in Q' <= 0."""
+    c = _backflow(cases.channel(30 if dim == 2 else 16, 10 if dim == 2 else 6, 0.01, dim=dim))
+    g = _gpu(c)
+    s = oracle.Sim(c)
+    g.step(1)
+    s.step(1)
+    dg, do = g.mass_flux(), s.diag()
+    print("  gpu", dg, "\n  oracle", do, flush=True)
+    assert do["uc_clamps"] == 1 and dg["uc_clamps"] == 1
+    assert do["u_conv"] == 0.0 and dg["u_conv"] == 0.0
+    assert do["q_in"] * do["q_out"] <= 0.0 and dg["q_in"] * dg["q_out"] <= 0.0
+    assert do["chi"] == 1.0 and dg["chi"] == 1.0
+    assert _compare_state(g, s) < 1e-5
 
 
 @pytest.mark.parametrize("name,make", [
