@@ -9,10 +9,12 @@ taken here:
 * a droplet is a face-connected component of it inside the main channel
   downstream of the junction, and its diameter is that of the disc (2-D) or
   ball (3-D) of the same area or volume;
-* the generation period is the mean interval between droplet passages through
-  a cross-section of the main channel, after the first two passages are
-  discarded; fewer than three remaining passages leave it undefined
-  (censored).  T* = T u_c / W.
+* the generation period is the median interval between droplet passages
+  through a cross-section of the main channel, after the first two passages
+  are discarded; fewer than three remaining passages leave it undefined
+  (censored).  The median keeps one irregular passage (a droplet that breaks
+  up in the channel, a front that recedes and returns between two samples)
+  from moving the period.  T* = T u_c / W.
 
 The GPU does the node work (``lbm_probe``: passage counts; ``lbm_components``:
 connected components); this module turns counts and components into labels.
@@ -46,12 +48,12 @@ def passages(series, on: int = 1) -> np.ndarray:
 
 
 def period(series, every: int, skip: int = 2):
-    """Mean interval (in steps) between passages after the first ``skip``;
+    """Median interval (in steps) between passages after the first ``skip``;
     None when fewer than three passages remain."""
     ev = passages(series)[skip:]
     if len(ev) < 3:
         return None
-    return float(np.diff(ev).mean() * every)
+    return float(np.median(np.diff(ev)) * every)
 
 
 def tjunction_regions(case):

@@ -4,7 +4,7 @@ at the coexisting densities), for the GPU comparison in
 tests/test_gpu_labels.py.
 
 The labels are those of Sec. III D as read in the labelling code (A30):
-* the generation period: mean interval between the passages of droplet
+* the generation period: median interval between the passages of droplet
   fronts through a cross-section of the channel core at mid-length (counts
   of nodes whose dispersed density exceeds the midpoint of the bulk
   densities, sampled every 100 steps; the first two passages are the
@@ -63,7 +63,7 @@ def main(out):
             print(f"[golden] step {(k + 1) * EVERY}: {len(diam)} droplet samples", flush=True)
     on = np.asarray(series) >= 1
     ev = (np.nonzero(on[1:] & ~on[:-1])[0] + 1)[2:]
-    period = float(np.diff(ev).mean() * EVERY) if len(ev) >= 3 else None
+    period = float(np.median(np.diff(ev)) * EVERY) if len(ev) >= 3 else None
     res = {"case": "coflow3d_quarter", "steps": STEPS, "every": EVERY, "threshold": thr,
            "period_steps": period, "passages": int(len(ev) + 2),
            "diameter": float(np.mean(diam)) if diam else None, "diameter_samples": len(diam),

@@ -24,8 +24,15 @@ def test_passages_and_period():
         s[t:t + 6] = 5            # a droplet crossing the probe for 6 samples
     ev = labels.passages(s)
     assert list(ev) == starts
-    # first two discarded; intervals 19, 22, 19, 18 samples
-    assert labels.period(s, every) == np.mean([19, 22, 19, 18]) * every
+    # first two discarded; intervals 19, 22, 19, 18 samples, median 19
+    assert labels.period(s, every) == 19 * every
+    # one passage counted twice (a front that recedes and returns) splits an
+    # interval into 3 + 16: the median moves to a neighbouring interval
+    # (18 samples), where the mean would drop to 15.6
+    s2 = s.copy()
+    s2[95] = 0
+    assert list(labels.passages(s2)) == [10, 30, 52, 71, 93, 96, 112, 130]
+    assert labels.period(s2, every) == 18 * every
     # fewer than three passages after the first two: censored
     assert labels.period(s[:80], every) is None
 
