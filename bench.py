@@ -326,7 +326,7 @@ def main():
         "hbm_frac_step": round(step_gbs / HBM_PEAK_GBS, 4),
         "roofline": roof,
         "cpu_baseline": cpu,
-        "kernel_ms": {"main": kms[0], "psi": kms[4], "outlet": kms[1], "inlet": kms[2], "outlet_fill": kms[3]},
+        "kernel_ms": {"main": kms[0], "psi": kms[4], "faces": kms[1], "inlet_uc": kms[2], "outlet_fill": kms[3]},
         "finite": finite,
         "extra": extra,
     }

@@ -129,6 +129,8 @@ typedef struct {
     int64_t step;
     double q_in;     /* sum over inlet nodes of rho u . n_inward      (eq. 23 numerator)   */
     double q_out;    /* sum over the x_{N-1} column of rho u . n_out  (eq. 23 denominator) */
+                     /* (both summed exactly with every term on a grid of 2^-40, so they do
+                      * not depend on the launch shape; |q| < 2^23) */
     double chi;      /* eq. (23) coefficient applied (1 if uncorrected or undefined) */
     double u_conv;   /* eq. (21) convective velocity after the clamp at 0 */
     double mass[2];  /* current total mass of each component over fluid nodes */
@@ -192,9 +194,11 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *f_host, size_t bytes);
 /* Measurement hook: enqueues n steps like lbm_step, bracketing every kernel
  * launch with HIP events on the context stream, then synchronises and writes
  * the mean duration in milliseconds of each launch kind into ms[5]:
- * [0] the node update, [1] the eq. (23) sums and the outlet collision, [2] the inlet
- * reconstruction, [3] the outlet fill, [4] the density pass that precedes
- * the node update in the two-pass mode (0 where a kind is not launched). */
+ * [0] the node update, [1] the first face launch (chi of eq. 23, the outlet
+ * collision and, unless one of them streams from the outlet column, the inlet
+ * nodes), [2] the inlet nodes left over and the partial sums of eq. (21),
+ * [3] the outlet fill, [4] the density pass that precedes the node update in
+ * the two-pass mode (0 where a kind is not launched). */
 lbm_status lbm_time_kernels(lbm_ctx *ctx, int64_t n, double *ms);
 
 /* Number of node-update configurations of the tuning space for dim (2 or 3),

@@ -17,12 +17,15 @@
 //                    in the fused mode; mirror ghost layers at open faces,
 //                    eqs. 24-25), force
 //                    (eqs. 10-11), common velocity (eqs. 7-8), MRT collision
-//                    (eq. 1); FP64 mass flow rho u.n of every inlet node and
-//                    x_{N-1} node into its face slot (eq. 23)
-//   k_outlet         chi = Q_in / Q' (eq. 23) and the collision of the outlet
-//                    column with the corrected normal velocity (eq. 22)
+//                    (eq. 1); the mass flows rho u.n of the inlet nodes and
+//                    of the x_{N-1} nodes summed exactly (eq. 23)
+//   k_faces          chi = Q_in / Q' (eq. 23) and the collision of the outlet
+//                    column with the corrected normal velocity (eq. 22); the
+//                    inlet nodes too when none of them pulls from the outlet
+//                    column
 //   k_inlet          alpha-corrected NEQ extrapolation (eqs. 13-19) into the
-//                    padding slots; partial sums of eq. (21)
+//                    padding slots (the inlet nodes k_faces did not take);
+//                    partial sums of eq. (21)
 //   k_outlet_fill    convective outflow (eq. 20) into the padding slots
 #pragma once
 
@@ -406,6 +409,17 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
 }
 
 // ---------------------------------------------------------------------------
+// The sums Q_in and Q' of eq. (23) as integers in units of 2^-40.  Each term
+// rho u.n (the FP64 product of two floats) is rounded once to that grid; the
+// integer sums are then exact, so they do not depend on which block adds
+// which term or in what order (every launch shape and tile configuration
+// gives the same bits).  The grid is far below FP32 resolution; the range
+// holds |Q| < 2^23.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long flow_fix(double q) { return __double2ll_rn(q * 0x1p40); }
+__device__ __forceinline__ double flow_unfix(unsigned long long v) { return (double)(long long)v * 0x1p-40; }
+
+// ---------------------------------------------------------------------------
 // k_main: the fused per-node update as a sweep along the last lattice axis
 // (y in 2-D, z in 3-D).  A block owns a lateral tile (TX in 2-D, TX x TY in
 // 3-D) and a chunk of ZC planes of the sweep axis; it advances W planes per
@@ -430,7 +444,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                                           const uint32_t *__restrict__ type, const float2 *__restrict__ psi,
                                           const float2 *__restrict__ ref, const Geometry &g, const Physics &ph,
                                           const Boundary &bd, int tiles_x, int tiles_y, int item,
-                                          int *__restrict__ flag)
+                                          int *__restrict__ flag, unsigned long long *__restrict__ qacc)
 {
     constexpr int Q = Lat<DIM>::Q;
     constexpr int LY = DIM == 3 ? TY : 1;          // lateral y extent of the tile
@@ -452,6 +466,11 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
 
     const __amdgpu_buffer_rsrc_t rs0 = comp_rsrc<STORE>(src, 0, Q, g.Ppad);
     const __amdgpu_buffer_rsrc_t rs1 = comp_rsrc<STORE>(src, 1, Q, g.Ppad);
+    // the item's share of the eq. (23) sums (fixed point, see flow_fix),
+    // gathered by LDS atomics at the face nodes, so that nothing is held in
+    // registers across the sweep
+    __shared__ unsigned long long s_q[2];
+    if (threadIdx.x == 0) s_q[0] = s_q[1] = 0ull;
     __syncthreads();                               // the ring of a previous item is free
     {
         const int ns = g.n[DIM - 1];
@@ -687,11 +706,11 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                     if (tw & T_XPRIME) {
                         const float un = bd.out_sign * pick3(u, bd.out_axis);
                         bd.faceU[slot] = un;
-                        bd.faceQ[slot] = (double)rt * (double)un;
+                        atomicAdd(&s_q[1], (unsigned long long)flow_fix((double)rt * (double)un));
                     }
                     if (tw & T_INLET) {
                         const Patch pt = bd.patch[(tw & T_PATCH_MASK) >> T_PATCH_SHIFT];
-                        bd.faceQ[slot] = (double)rt * (double)(pt.sign * pick3(u, pt.axis));
+                        atomicAdd(&s_q[0], (unsigned long long)flow_fix((double)rt * (double)(pt.sign * pick3(u, pt.axis))));
                     }
                     if ((tw & T_OUTLET) && bd.chi_on) continue;   // collided by k_outlet
                 }
@@ -740,6 +759,11 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
             }
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_q[0]) atomicAdd(qacc, s_q[0]);
+        if (s_q[1]) atomicAdd(qacc + 1, s_q[1]);
+    }
 }
 
 // One context: one block per work item (tiles that hold fluid, in tile
@@ -755,7 +779,7 @@ void k_main(const typename Codec<STORE>::T *__restrict__ src,
                                               const float2 *__restrict__ psi, const float2 *__restrict__ ref,
                                               Geometry g, Physics ph, Boundary bd, int tiles_x, int tiles_y,
                                               int n_items, const int *__restrict__ item_list,
-                                              int *__restrict__ flag)
+                                              int *__restrict__ flag, unsigned long long *__restrict__ qacc)
 {
     // blocks go round-robin to the 8 XCDs (blockIdx % 8); each XCD takes
     // groups of MAIN_XCD_GROUP consecutive work items, so that all XCDs sweep
@@ -766,7 +790,7 @@ void k_main(const typename Codec<STORE>::T *__restrict__ src,
     const int k = ((S / MAIN_XCD_GROUP) * 8 + r) * MAIN_XCD_GROUP + S % MAIN_XCD_GROUP;
     if (k < n_items)
         main_item<DIM, STORE, PSRC, TX, TY, W, ZC, KEEPB>(src, dst, type, psi, ref, g, ph, bd, tiles_x, tiles_y,
-                                                          item_list[k], flag);
+                                                          item_list[k], flag, qacc);
 }
 
 // ---------------------------------------------------------------------------
@@ -925,43 +949,38 @@ __device__ __forceinline__ double chi_of(double qin, double qout)
 }
 
 // ---------------------------------------------------------------------------
-// k_chi: eq. (23).  Q_in over the inlet nodes and Q' over the x_{N-1} column,
-// from the per-node mass flows k_main left in the face slots, summed by one
-// block in the fixed record order (independent of every launch shape).
+// eq. (23) from the sums the node update left in acc (this step's parity):
+// every thread of the first face launch forms chi itself; one thread records
+// Q_in, Q' and chi and clears the sums of the other parity for the next step.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void chi_body(const Boundary &bd)
+__device__ __forceinline__ double chi_from(const Boundary &bd, const unsigned long long *acc,
+                                           unsigned long long *next, bool record)
 {
-    __shared__ double s_red[2 * CHI_NT / 64];
-    double qin = 0.0, qout = 0.0;
-    // unrolled so that the loads of several iterations are in flight at once
-    // (the sums still run in the same sequential order per thread)
-#pragma unroll 8
-    for (int j = threadIdx.x; j < bd.n_in; j += CHI_NT) qin += bd.faceQ[j];
-#pragma unroll 8
-    for (int j = threadIdx.x; j < bd.n_xp; j += CHI_NT) qout += bd.faceQ[bd.n_in + j];
-    block_sum2<CHI_NT>(qin, qout, s_red);
-    if (threadIdx.x == 0) {
+    const double qin = flow_unfix(acc[0]), qout = flow_unfix(acc[1]);
+    const double chi = (bd.has_outlet && bd.chi_on) ? chi_of(qin, qout) : 1.0;
+    if (record) {
         bd.scal[SC_QIN] = qin;
         bd.scal[SC_QOUT] = qout;
-        bd.scal[SC_CHI] = (bd.has_outlet && bd.chi_on) ? chi_of(qin, qout) : 1.0;
+        bd.scal[SC_CHI] = chi;
+        next[0] = 0ull;
+        next[1] = 0ull;
     }
+    return chi;
 }
 
-static __global__ __launch_bounds__(CHI_NT) void k_chi(Boundary bd) { chi_body(bd); }
-
 // ---------------------------------------------------------------------------
-// k_outlet: the collision of the outlet column with eq. (22), chi from k_chi.
+// The collision of the outlet column with eq. (22) for a given chi (eq. 23).
 // ---------------------------------------------------------------------------
 template <int DIM, int STORE>
 __device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>::T *__restrict__ src,
                                                     typename Codec<STORE>::T *__restrict__ dst,
                                                     const uint32_t *__restrict__ type,
                                                     const float2 *__restrict__ psi, const float2 *__restrict__ ref,
-                                                    Geometry g, Physics ph, Boundary bd, int *__restrict__ flag)
+                                                    Geometry g, Physics ph, Boundary bd, int *__restrict__ flag,
+                                                    double chi)
 {
     using T = typename Codec<STORE>::T;
     constexpr int Q = Lat<DIM>::Q;
-    const double chi = bd.scal[SC_CHI];
     const int r = blk * FACE_NT + threadIdx.x;
     if (r >= bd.n_out) return;
     const OutletRec rec = bd.out[r];
@@ -1020,16 +1039,6 @@ __device__ __forceinline__ void outlet_body(int blk, const typename Codec<STORE>
     });
 }
 
-template <int DIM, int STORE>
-__global__ __launch_bounds__(FACE_NT) void k_outlet(const typename Codec<STORE>::T *__restrict__ src,
-                                                    typename Codec<STORE>::T *__restrict__ dst,
-                                                    const uint32_t *__restrict__ type,
-                                                    const float2 *__restrict__ psi, const float2 *__restrict__ ref,
-                                                    Geometry g, Physics ph, Boundary bd, int *__restrict__ flag)
-{
-    outlet_body<DIM, STORE>((int)blockIdx.x, src, dst, type, psi, ref, g, ph, bd, flag);
-}
-
 // ---------------------------------------------------------------------------
 // k_inlet: blocks [0, nb_in) rebuild the entering populations of the inlet
 // nodes (eqs. 13-19); blocks [nb_in, ...) sum u.n_o over x_{N-1} (eq. 21).
@@ -1086,7 +1095,15 @@ __device__ __forceinline__ void inlet_body(int blk, typename Codec<STORE>::T *__
             float f1[Q];
             const float2 r1f = psi[rec.b1];
             const float rref1 = k == 0 ? r1f.x : r1f.y;
-            gather<DIM, STORE>(dk, g, p1, tw1, x1, y1, z1, f1, rref1);
+            // the populations that leave x1: the entering ones are replaced
+            // below, so their ghost slots (a line of their own when the face
+            // is normal to the fastest memory axis) are not read
+            static_for<Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                f1[i] = e_axis<DIM>(i, pt.axis) * pt.sign > 0
+                            ? 0.0f
+                            : gather1<DIM, STORE>(dk, g, p1, tw1, x1, y1, z1, i, rref1);
+            });
             // eq. (13)/(14) on the populations entering the domain
             static_for<Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
@@ -1178,6 +1195,27 @@ __global__ __launch_bounds__(FACE_NT) void k_inlet(typename Codec<STORE>::T *__r
                                                    int nb_in)
 {
     inlet_body<DIM, STORE>((int)blockIdx.x, dst, type, psi, g, bd, nb_in);
+}
+
+// ---------------------------------------------------------------------------
+// k_faces: the first launch after the node update.  chi from this step's
+// sums; blocks [0, nb_out) collide the outlet column, blocks [nb_out,
+// nb_out + nb_in) rebuild inlet nodes (only when no inlet node pulls from the
+// outlet column, checked at creation, so the two sets are independent).
+// ---------------------------------------------------------------------------
+template <int DIM, int STORE>
+__global__ __launch_bounds__(FACE_NT) void k_faces(const typename Codec<STORE>::T *__restrict__ src,
+                                                   typename Codec<STORE>::T *__restrict__ dst,
+                                                   const uint32_t *__restrict__ type,
+                                                   const float2 *__restrict__ psi, const float2 *__restrict__ ref,
+                                                   Geometry g, Physics ph, Boundary bd, int *__restrict__ flag,
+                                                   const unsigned long long *__restrict__ acc,
+                                                   unsigned long long *__restrict__ next, int nb_out, int nb_in)
+{
+    const int blk = (int)blockIdx.x;
+    const double chi = chi_from(bd, acc, next, blk == 0 && threadIdx.x == 0);
+    if (blk < nb_out) outlet_body<DIM, STORE>(blk, src, dst, type, psi, ref, g, ph, bd, flag, chi);
+    else if (blk - nb_out < nb_in) inlet_body<DIM, STORE>(blk - nb_out, dst, type, psi, g, bd, nb_in);
 }
 
 // ---------------------------------------------------------------------------
@@ -1459,15 +1497,17 @@ void k_main_batch(BatchTab t, int cur)
                                                           (const float2 *)m->psi[cur],
                                                           (const float2 *)m->psi[cur ^ 1], g, ph, bd,
                                                           m->tiles_x, m->tiles_y, m->item_list[w - t.item0[i]],
-                                                          m->flag);
+                                                          m->flag, bd.qacc + 2 * cur);
     }
 }
 
-// eq. (23) sums, one block per member
-static __global__ __launch_bounds__(CHI_NT) void k_chi_batch(BatchTab t)
+// eq. (23) from the sums of each member, one thread per member
+static __global__ __launch_bounds__(64) void k_chi_batch(BatchTab t, int cur)
 {
-    const Boundary bd = const_copy(&((CMember *)(t.m + blockIdx.x))->bd);
-    if (bd.n_in + bd.n_out > 0) chi_body(bd);
+    const int i = (int)(blockIdx.x * 64 + threadIdx.x);
+    if (i >= t.n) return;
+    const Boundary bd = const_copy(&((CMember *)(t.m + i))->bd);
+    (void)chi_from(bd, bd.qacc + 2 * cur, bd.qacc + 2 * (cur ^ 1), true);
 }
 
 template <int DIM, int STORE>
@@ -1476,9 +1516,10 @@ __global__ __launch_bounds__(FACE_NT) void k_outlet_batch(BatchTab t, int cur)
     using T = typename Codec<STORE>::T;
     const int i = member_of(t.out0, t.n, (int)blockIdx.x);
     CMember *m = (CMember *)(t.m + i);
+    const Boundary bd = const_copy(&m->bd);
     outlet_body<DIM, STORE>((int)blockIdx.x - t.out0[i], (const T *)m->f[cur], (T *)m->f[cur ^ 1], m->type,
                             (const float2 *)m->psi[cur], (const float2 *)m->psi[cur ^ 1], const_copy(&m->g),
-                            const_copy(&m->ph), const_copy(&m->bd), m->flag);
+                            const_copy(&m->ph), bd, m->flag, bd.scal[SC_CHI]);
 }
 
 template <int DIM, int STORE>

@@ -57,6 +57,8 @@ struct StepArgs {
     unsigned grid;
     double *orho, *ou;
     int *flag;
+    unsigned long long *qacc;   // eq. (23) sums of this step (Boundary::qacc at the step's parity)
+    unsigned long long *qnext;  // those of the other parity, cleared by the first face launch
     hipStream_t stream;
 };
 
@@ -72,8 +74,8 @@ template <int DIM> struct Launcher {
     static void psi(int storage, const StepArgs &a);
     static void moments(int storage, const StepArgs &a);
     static void main(int storage, int cfg, const StepArgs &a);
-    static void chi(const StepArgs &a);
-    static void outlet(int storage, const StepArgs &a, unsigned nb);
+    // chi; nb_out blocks of outlet collision and nb_in blocks of inlet nodes
+    static void faces(int storage, const StepArgs &a, int nb_out, int nb_in);
     static void inlet(int storage, const StepArgs &a, unsigned nb, int nb_in);
     static void outlet_fill(int storage, const StepArgs &a, unsigned nb);
     static void scatter(int storage, const StepArgs &a, const double *f, float2 *ref_out);

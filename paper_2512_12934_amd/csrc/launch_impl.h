@@ -2,6 +2,7 @@
 // translation unit per lattice.
 #pragma once
 
+#include <algorithm>
 #include <utility>
 
 #include "kernels.h"
@@ -21,7 +22,7 @@ void launch_cfg(const StepArgs &a)
     using T = typename Codec<STORE>::T;
     hipLaunchKernelGGL((k_main<DIM, STORE, c.psrc, c.tx, c.ty, c.w, c.zc, c.keepb>), dim3(a.grid), dim3(256), 0,
                        a.stream, (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.ph,
-                       a.bd, a.tiles_x, a.tiles_y, a.items, a.item_list, a.flag);
+                       a.bd, a.tiles_x, a.tiles_y, a.items, a.item_list, a.flag, a.qacc);
 }
 
 template <int DIM, int STORE, int... I>
@@ -39,7 +40,7 @@ void launch_batch_cfg(const BatchArgs &b)
     if (b.g_main)
         hipLaunchKernelGGL((k_main_batch<DIM, STORE, c.psrc, c.tx, c.ty, c.w, c.zc, c.keepb>), dim3(b.g_main),
                            dim3(256), 0, b.stream, b.t, b.cur);
-    if (b.g_chi) hipLaunchKernelGGL(k_chi_batch, dim3(b.g_chi), dim3(CHI_NT), 0, b.stream, b.t);
+    if (b.g_chi) hipLaunchKernelGGL(k_chi_batch, dim3(b.g_chi), dim3(64), 0, b.stream, b.t, b.cur);
     if (b.g_out)
         hipLaunchKernelGGL((k_outlet_batch<DIM, STORE>), dim3(b.g_out), dim3(FACE_NT), 0, b.stream, b.t, b.cur);
     if (b.g_inl)
@@ -100,19 +101,15 @@ void Launcher<DIM>::main(int storage, int cfg, const StepArgs &a)
 }
 
 template <int DIM>
-void Launcher<DIM>::chi(const StepArgs &a)
+void Launcher<DIM>::faces(int storage, const StepArgs &a, int nb_out, int nb_in)
 {
-    hipLaunchKernelGGL(k_chi, dim3(1), dim3(CHI_NT), 0, a.stream, a.bd);
-}
-
-template <int DIM>
-void Launcher<DIM>::outlet(int storage, const StepArgs &a, unsigned nb)
-{
+    // at least one block: it records chi and the sums and clears the next ones
+    const unsigned nb = (unsigned)std::max(1, nb_out + nb_in);
     with_store(storage, [&](auto sc) {
         using T = LBM_STORE_T(sc);
-        hipLaunchKernelGGL((k_outlet<DIM, decltype(sc)::value>), dim3(nb), dim3(FACE_NT), 0, a.stream,
+        hipLaunchKernelGGL((k_faces<DIM, decltype(sc)::value>), dim3(nb), dim3(FACE_NT), 0, a.stream,
                            (const T *)a.src, (T *)a.dst, a.type, (const float2 *)a.psi, a.ref, a.g, a.ph, a.bd,
-                           a.flag);
+                           a.flag, a.qacc, a.qnext, nb_out, nb_in);
     });
 }
 

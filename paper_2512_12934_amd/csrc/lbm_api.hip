@@ -42,11 +42,13 @@ struct Layout {
     int nb_mass = 0;
     bool boundary = false;
     // byte offsets into the workspace
-    size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qpart, o_ucpart, o_scal,
+    size_t o_fA, o_fB, o_type, o_bslot, o_faceF, o_faceU, o_in, o_out, o_qacc, o_ucpart, o_scal,
         o_flag, o_mpart, o_mout, o_patch, o_psi[2], o_items, o_hist, o_wallc, total;
     bool moving = false;
     int cfg = 0;                   // node-update configuration (launch.h)
     int psi_mode = 1;              // 1: psi array written by k_psi, 0: recomputed in k_main
+    bool inlet_early = true;       // no inlet node pulls from the collided outlet column, so the
+                                   // inlet nodes run in the outlet collision's launch
 };
 
 // Host-side static maps built from the configuration.
@@ -58,6 +60,7 @@ struct Maps {
     std::vector<InletRec> in;
     std::vector<OutletRec> out;
     int n_xp = 0;                  // fluid x_{N-1} nodes (slots n_in .. n_in + n_xp)
+    bool inlet_pulls_outlet = false;   // an inlet node x1 or x2 streams from an outlet node
 };
 
 int lat_Q(int dim) { return dim == 2 ? 9 : 19; }
@@ -372,6 +375,31 @@ std::string build_maps(const lbm_config *c, Maps &m)
         r.slot1 = m.bslot[r.b1];
         r.slot2 = c->solid[r.b2] ? r.slot1 : m.bslot[r.b2];
     }
+    // does the inlet rule read a population that the outlet collision
+    // writes?  It reads the streamed populations of x1 and x2, so it
+    // depends on the outlet column when one of them pulls from it
+    for (const auto &r : m.in) {
+        for (int k = 0; k < 2 && !m.inlet_pulls_outlet; k++) {
+            const int64_t b = k == 0 ? r.b1 : r.b2;
+            if (c->solid[b]) continue;
+            const int xc[3] = {(int)(b % c->n[0]), (int)((b / c->n[0]) % c->n[1]),
+                               (int)(b / ((int64_t)c->n[0] * c->n[1]))};
+            for (int i = 0; i < Q; i++) {
+                int e[3];
+                dir(c->dim, i, e);
+                int sx[3] = {xc[0] - e[0], xc[1] - e[1], xc[2] - e[2]};
+                bool inside = true;
+                for (int a = 0; a < c->dim; a++)
+                    if (sx[a] < 0 || sx[a] >= c->n[a]) {
+                        if (c->periodic[a]) sx[a] = (sx[a] + c->n[a]) % c->n[a];
+                        else inside = false;
+                    }
+                if (!inside) continue;
+                const int64_t sb = (int64_t)sx[0] + (int64_t)c->n[0] * ((int64_t)sx[1] + (int64_t)c->n[1] * sx[2]);
+                if (m.type[sb] & T_OUTLET) m.inlet_pulls_outlet = true;
+            }
+        }
+    }
     for (auto &r : m.out) {
         r.slotN = m.bslot[r.bN];
         r.slotP = r.bP >= 0 ? m.bslot[r.bP] : -1;
@@ -468,6 +496,7 @@ Layout make_layout(const Canon &k, const Maps &m)
     L.boundary = L.n_in > 0 || c->has_outlet;
     L.nb_in = (int)((L.n_in + FACE_NT - 1) / FACE_NT);
     L.nb_out = (int)((L.n_out + FACE_NT - 1) / FACE_NT);
+    L.inlet_early = !(c->has_outlet && c->outlet.chi_on) || !m.inlet_pulls_outlet;
     L.nb_mass = (int)std::min<int64_t>(1024, (g.N + 255) / 256);
     const size_t fbytes = (size_t)2 * L.Q * g.Ppad * (L.storage == LBM_STORE_F32 ? 4 : 2);
     size_t o = 0;
@@ -480,7 +509,7 @@ Layout make_layout(const Canon &k, const Maps &m)
     L.o_faceU = take((size_t)L.n_slots * 4);
     L.o_in = take((size_t)L.n_in * sizeof(InletRec));
     L.o_out = take((size_t)L.n_out * sizeof(OutletRec));
-    L.o_qpart = take((size_t)L.n_slots * 8);
+    L.o_qacc = take(4 * sizeof(unsigned long long));
     L.o_ucpart = take((size_t)std::max(L.nb_out, 1) * 16);
     L.o_scal = take(SC_COUNT * 8);
     L.o_flag = take(4);
@@ -628,6 +657,8 @@ StepArgs step_args(const lbm_ctx *c, double *orho = nullptr, double *ou = nullpt
     a.orho = orho;
     a.ou = ou;
     a.flag = c->flag();
+    a.qacc = c->bd.qacc + 2 * c->cur;
+    a.qnext = c->bd.qacc + 2 * (c->cur ^ 1);
     a.stream = c->stream;
     return a;
 }
@@ -665,13 +696,17 @@ template <int DIM> struct Ops {
         main_kernel(c, ev);
         if (L.boundary) {
             const StepArgs a = step_args(c);
+            // chi, the outlet collision and (when independent of it) the inlet nodes
+            const int nb_coll = c->bd.has_outlet && c->bd.chi_on ? L.nb_out : 0;
+            const int nb_in_early = L.inlet_early ? L.nb_in : 0;
             if (ev) (void)hipEventRecord(ev[2], c->stream);
-            Lx::chi(a);
-            if (c->bd.has_outlet && c->bd.chi_on && L.nb_out > 0) Lx::outlet(L.storage, a, (unsigned)L.nb_out);
+            Lx::faces(L.storage, a, nb_coll, nb_in_early);
             if (ev) (void)hipEventRecord(ev[3], c->stream);
-            if (L.nb_in + L.nb_out > 0) {
+            // the remaining inlet nodes, then the U_c partial sums of eq. (21)
+            const int nb_in_late = L.nb_in - nb_in_early;
+            if (nb_in_late + L.nb_out > 0) {
                 if (ev) (void)hipEventRecord(ev[4], c->stream);
-                Lx::inlet(L.storage, a, (unsigned)(L.nb_in + L.nb_out), L.nb_in);
+                Lx::inlet(L.storage, a, (unsigned)(nb_in_late + L.nb_out), nb_in_late);
                 if (ev) (void)hipEventRecord(ev[5], c->stream);
             }
             if (L.nb_out > 0) {
@@ -847,7 +882,7 @@ lbm_status lbm_create(const lbm_config *cfg, void *dev_ws, size_t ws_bytes, void
     bd.n_xp = m.n_xp;
     bd.faceF = (float *)(ws + L.o_faceF);
     bd.faceU = (float *)(ws + L.o_faceU);
-    bd.faceQ = (double *)(ws + L.o_qpart);
+    bd.qacc = (unsigned long long *)(ws + L.o_qacc);
     bd.ucpart = (double *)(ws + L.o_ucpart);
     bd.n_ucpart = L.nb_out;
     bd.scal = (double *)(ws + L.o_scal);
@@ -1043,7 +1078,8 @@ lbm_status lbm_time_kernels(lbm_ctx *c, int64_t n, double *ms)
     HIPCHECK(c, hipGetLastError());
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     c->steps += n;
-    const bool used[5] = {true, c->L.boundary, c->L.boundary && c->L.nb_in + c->L.nb_out > 0,
+    const bool used[5] = {true, c->L.boundary,
+                          c->L.boundary && (c->L.inlet_early ? 0 : c->L.nb_in) + c->L.nb_out > 0,
                           c->L.boundary && c->L.nb_out > 0, c->L.psi_mode != 0};
     for (int k = 0; k < 5; k++) {
         double acc = 0.0;
@@ -1298,7 +1334,7 @@ lbm_status lbm_batch_create(const lbm_config *cfgs, int n, void *dev_ws, size_t 
     const int items = item0[n];
     b->g_main = (unsigned)std::min((items + 7) / 8 * 8, 2048);
     b->g_psi = (unsigned)psi0[n];
-    b->g_chi = faces ? (unsigned)n : 0u;
+    b->g_chi = faces ? (unsigned)((n + 63) / 64) : 0u;
     b->g_out = (unsigned)out0[n];
     b->g_inl = (unsigned)inl0[n];
     b->g_fill = (unsigned)fill0[n];

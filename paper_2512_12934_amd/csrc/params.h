@@ -83,7 +83,10 @@ struct Boundary {
                               // [n_in, n_in + n_xp) the x_{N-1} nodes, both in record order
     float *faceF;             // [slots][2][3] force of this step at role nodes
     float *faceU;             // [slots] normal velocity at x' (outward)
-    double *faceQ;            // [slots] rho u.n at inlet and x' nodes (eq. 23 terms)
+    // [2 parities][2] the eq. 23 sums Q_in and Q' of a step as integers in
+    // units of 2^-40 (see flow_fix): the node update adds into the pair of
+    // the step's parity, the first face launch reads it and clears the other
+    unsigned long long *qacc;
     double *ucpart;           // [inlet-kernel blocks][2] partial sum of u.n at x' and count
     int n_ucpart;
     double *scal;             // device scalars, see SC_* below
@@ -103,8 +106,6 @@ struct Boundary {
 // Threads per block of the face kernels (one wave: the face node counts are
 // small, so narrow blocks spread the uncoalesced face gathers over more CUs).
 constexpr int FACE_NT = 64;
-// Threads of the single block that forms the eq. 23 sums.
-constexpr int CHI_NT = 1024;
 // Consecutive node-update work items that one XCD takes per turn.
 constexpr int MAIN_XCD_GROUP = 4;
 
