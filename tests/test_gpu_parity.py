@@ -108,6 +108,10 @@ SMALL = [
     ("inlet_x2_solid", lambda: _x2_solid(cases.channel(30, 10, 0.01))),
     ("inlet_x2_solid3d", lambda: _x2_solid(cases.channel(20, 6, 0.01, dim=3))),
     ("backflow", lambda: _backflow(cases.channel(30, 10, 0.01))),
+    # channels three nodes long: x2 of every inlet node streams from the outlet
+    # column, so the inlet runs after the outlet collision instead of beside it
+    ("short_channel", lambda: cases.channel(3, 8, 0.01)),
+    ("short_channel3d", lambda: cases.channel(3, 5, 0.01, dim=3)),
 ]
 
 
