@@ -712,7 +712,7 @@ __device__ __forceinline__ void main_item(const typename Codec<STORE>::T *__rest
                         const Patch pt = bd.patch[(tw & T_PATCH_MASK) >> T_PATCH_SHIFT];
                         atomicAdd(&s_q[0], (unsigned long long)flow_fix((double)rt * (double)(pt.sign * pick3(u, pt.axis))));
                     }
-                    if ((tw & T_OUTLET) && bd.chi_on) continue;   // collided by k_outlet
+                    if ((tw & T_OUTLET) && bd.chi_on) continue;   // collided by the face launch (k_faces)
                 }
 
                 // ---- MRT collision of each component, stored at x
