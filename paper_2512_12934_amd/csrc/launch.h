@@ -27,6 +27,10 @@ constexpr TileCfg CFG2[] = {
     {1, 64, 1, 8, 16, 1},
     {1, 64, 1, 16, 32, 1},
     {1, 32, 1, 16, 32, 1},
+    // shallow chunks: four times the work items, for small domains whose
+    // deeper items would leave most CUs idle
+    {1, 32, 1, 8, 8, 1},
+    {1, 64, 1, 4, 8, 1},
 };
 constexpr TileCfg CFG3[] = {
     {1, 32, 8, 4, 16, 1},
