@@ -40,6 +40,12 @@ constexpr TileCfg CFG3[] = {
     {1, 32, 8, 4, 32, 1},
     {1, 32, 8, 8, 16, 1},
     {0, 32, 8, 4, 16, 1},
+    // shallow chunks: four (eight) times the work items of the 16-plane
+    // shapes, so the last wave of blocks leaves fewer CUs idle (the picks for
+    // the co-flow device at full and at quarter scale)
+    {1, 32, 8, 4, 4, 1},
+    {1, 64, 4, 4, 4, 1},
+    {1, 32, 8, 2, 2, 1},
 };
 constexpr int NCFG2 = sizeof(CFG2) / sizeof(CFG2[0]);
 constexpr int NCFG3 = sizeof(CFG3) / sizeof(CFG3[0]);
