@@ -31,6 +31,7 @@ constexpr TileCfg CFG2[] = {
     // deeper items would leave most CUs idle
     {1, 32, 1, 8, 8, 1},
     {1, 64, 1, 4, 8, 1},
+    {0, 32, 1, 8, 8, 1},
 };
 constexpr TileCfg CFG3[] = {
     {1, 32, 8, 4, 16, 1},
